@@ -1,0 +1,198 @@
+/*
+ * bfs.h -- C ABI of libbfsmi, a single-GPU (gfx950) level-synchronous
+ * breadth-first search.
+ *
+ * The search is the local frontier expansion of Bisson, Bernaschi and
+ * Mastrostefano, "Parallel Distributed Breadth First Search on the Kepler
+ * Architecture" (2014), run by one GPU over the whole graph:
+ *   - per level, an exclusive scan of the frontier vertices' degrees and a
+ *     search of that cumulative array that maps every frontier edge to a
+ *     thread (Section 3.4, the mapping formula and Algorithm 3; multi-edge
+ *     threads, Section 3.4.1);
+ *   - a visited bitmap with one bit per vertex, probed with a plain read and
+ *     claimed with an atomic OR whose returned word picks the single winner
+ *     that sets the vertex's level and predecessor (Algorithm 3);
+ *   - compaction of the winners into the next frontier queue (Algorithm 3,
+ *     the per-destination counter, here one queue and one counter);
+ *   - a bitmap form of the frontier, used when the frontier list would be
+ *     longer than the bitmap (threshold T = ceil(V / 32) vertices,
+ *     Section 5), converted back to a list by ballot/prefix compaction.
+ * Conventions (Algorithm 2 initialisation): level[root] = 0,
+ * parent[root] = root, unreached vertices have level -1 and parent -1.
+ *
+ * All functions return an int status.  No C++ exception crosses the ABI.
+ * The message of the last error on the calling thread is bfs_last_error().
+ *
+ * Memory ownership: the caller owns every device buffer.  A graph handle
+ * borrows the CSR arrays and the workspace until bfs_graph_destroy().  The
+ * library allocates no device memory on the search path; it allocates a
+ * small pinned host block per graph handle at creation.
+ *
+ * Streams: hip_stream is a hipStream_t passed as void* (NULL = the null
+ * stream).  bfs_run / bfs_run_batch enqueue on that stream and return after
+ * the stream's work for the call has completed.
+ */
+#ifndef BFSMI_BFS_H
+#define BFSMI_BFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define BFS_OK             0
+#define BFS_PENDING        1   /* bfs_poll: the query has not finished      */
+#define BFS_ERR_INVALID   -1   /* null pointer, bad size or out-of-range id  */
+#define BFS_ERR_NO_DEVICE -2   /* no usable HIP device                        */
+#define BFS_ERR_HIP       -3   /* a HIP runtime call failed                   */
+#define BFS_ERR_WORKSPACE -4   /* workspace smaller than bfs_workspace_bytes  */
+#define BFS_ERR_DEPTH     -5   /* a batch level does not fit int8 (> 127)     */
+#define BFS_ERR_BUSY      -6   /* the graph handle is in use by another call  */
+#define BFS_ERR_BUDGET    -7   /* a server graph can never fit the arena      */
+#define BFS_ERR_TICKET    -8   /* unknown or already collected ticket         */
+
+/* Flags for bfs_workspace_bytes / bfs_graph_create. */
+#define BFS_VALIDATE_CSR  0x1u /* check offsets and column ids on creation    */
+#define BFS_WS_BATCH      0x2u /* also reserve the multi-source batch arrays  */
+
+/* Options for bfs_set_option (tuning knobs; defaults are sensible). */
+#define BFS_OPT_EDGES_PER_THREAD 1 /* 1, 2, 4 or 8 frontier edges per thread    */
+#define BFS_OPT_FRONTIER_MODE    2 /* 0 auto (list/bitmap by threshold),
+                                      1 list only, 2 bitmap whenever possible */
+#define BFS_OPT_LOOP_DRIVER      3 /* 0 auto, 1 host loop (one 4-byte read per
+                                      level), 2 device loop for small frontiers */
+#define BFS_OPT_BATCH_TILE       4 /* edges per workgroup in the batch kernels:
+                                      256, 512, 1024 or 2048                  */
+#define BFS_OPT_GRID_WGS         5 /* workgroups per CU for grid-stride kernels */
+
+typedef struct bfs_graph bfs_graph;
+typedef struct bfs_server bfs_server;
+
+typedef struct bfs_stats {
+    int32_t levels;         /* number of non-empty frontiers, root's included   */
+    int32_t bitmap_levels;  /* levels whose next frontier used the bitmap form  */
+    int64_t reached;        /* vertices reached (sum of frontier sizes)         */
+    int64_t edges_scanned;  /* sum of out-degrees of reached vertices           */
+    double  device_ms;      /* stream time of the call (HIP events)             */
+} bfs_stats;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *bfs_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int bfs_version(void);
+
+/*
+ * Device workspace needed by a graph with V vertices and nnz directed CSR
+ * entries.  Pure host arithmetic: never touches the device.
+ *   V    : 1 .. 2^31 - 1;  nnz : 0 .. 2^62
+ *   flags: BFS_WS_BATCH adds the batch arrays (3 * 8 * V bytes).
+ * Errors: BFS_ERR_INVALID for out-of-range sizes or a null bytes pointer.
+ */
+int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t *bytes);
+
+/*
+ * Create a graph handle over a CSR that is already in device memory.
+ *   d_row_offsets: int64[V + 1], d_row_offsets[0] = 0, non-decreasing,
+ *                  d_row_offsets[V] = nnz (device, borrowed)
+ *   d_col        : int32[nnz] neighbour ids in [0, V) (device, borrowed)
+ *   d_workspace  : >= bfs_workspace_bytes(V, nnz, flags) bytes, 256-byte
+ *                  aligned (device, borrowed)
+ * The graph may be directed; the search follows out-edges.  Duplicates and
+ * self-loops are legal.  With BFS_VALIDATE_CSR the offsets and ids are
+ * checked on the device (BFS_ERR_INVALID on failure).  Synchronous.
+ * Errors: BFS_ERR_INVALID, BFS_ERR_WORKSPACE, BFS_ERR_NO_DEVICE, BFS_ERR_HIP.
+ */
+int bfs_graph_create(bfs_graph **g, int32_t V, int64_t nnz,
+                     const int64_t *d_row_offsets, const int32_t *d_col,
+                     void *d_workspace, size_t ws_bytes, uint32_t flags,
+                     void *hip_stream);
+
+/* Release the handle (not the borrowed buffers).  NULL is a no-op. */
+int bfs_graph_destroy(bfs_graph *g);
+
+/* Set a tuning option (BFS_OPT_*).  BFS_ERR_INVALID for unknown keys or
+ * values. */
+int bfs_set_option(bfs_graph *g, int key, int64_t value);
+int bfs_get_option(bfs_graph *g, int key, int64_t *value);
+
+/*
+ * Single-root search.
+ *   root     : 0 <= root < V
+ *   d_levels : int32[V] (device, caller-owned), written completely
+ *   d_parents: int32[V] (device) or NULL to skip predecessors
+ *   st       : nullable
+ * Returns after the search has completed on hip_stream.  A handle runs one
+ * search at a time: a concurrent call returns BFS_ERR_BUSY.
+ */
+int bfs_run(bfs_graph *g, int32_t root, int32_t *d_levels, int32_t *d_parents,
+            void *hip_stream, bfs_stats *st);
+
+/*
+ * Multi-source batch: n_roots independent searches run together, one bit of
+ * a 64-bit mask per root and vertex, the union frontier expanded once per
+ * level.  Needs a graph created with BFS_WS_BATCH.
+ *   h_roots : int32[n_roots] (host), each in [0, V); repeats are allowed
+ *   n_roots : 1 .. 64
+ *   d_levels: int8[n_roots][V] (device, row-major by root), written
+ *             completely; -1 = unreached
+ * BFS_ERR_DEPTH if some root's search goes deeper than 127 levels (the rows
+ * are then incomplete).  st->reached / edges_scanned describe the union.
+ */
+int bfs_run_batch(bfs_graph *g, const int32_t *h_roots, int32_t n_roots,
+                  int8_t *d_levels, void *hip_stream, bfs_stats *st);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: a resident pool of graphs, queries admitted by an HBM budget and
+ * batched per graph into multi-source lanes at level boundaries.          */
+
+typedef struct bfs_server_config {
+    int32_t max_lanes;       /* lanes per graph batch, 1 .. 64 (default 64)   */
+    int32_t max_inflight;    /* graphs with a running batch at once (>= 1)    */
+    int64_t level_budget_us; /* unused by default (0)                         */
+} bfs_server_config;
+
+typedef struct bfs_timing {
+    int64_t submit_ns;  /* steady-clock times in nanoseconds */
+    int64_t admit_ns;
+    int64_t done_ns;
+    int32_t levels;     /* depth of the query's search + 1 */
+    int32_t lanes_in_batch;
+} bfs_timing;
+
+/*
+ * Create a server over a caller-owned device arena of arena_bytes (the HBM
+ * budget for per-graph batch state and per-query outputs).  cfg nullable.
+ */
+int bfs_server_create(bfs_server **s, void *d_arena, size_t arena_bytes,
+                      const bfs_server_config *cfg);
+
+/* Register a graph (created without BFS_WS_BATCH is fine); the server does
+ * not own it.  BFS_ERR_BUDGET if this graph's batch state can never fit. */
+int bfs_server_add_graph(bfs_server *s, bfs_graph *g, int32_t *graph_id);
+
+/* Enqueue a single-root query; non-blocking.  *ticket identifies it. */
+int bfs_submit(bfs_server *s, int32_t graph_id, int32_t root, uint64_t *ticket);
+
+/*
+ * Poll a query.  BFS_PENDING while it runs.  On BFS_OK, if dst_levels is not
+ * NULL, copies int32[V] levels of the query's graph into it (host memory),
+ * fills *t if not NULL, and retires the ticket.  BFS_ERR_TICKET for unknown
+ * or retired tickets.
+ */
+int bfs_poll(bfs_server *s, uint64_t ticket, int32_t *dst_levels, bfs_timing *t);
+
+/* Block until every submitted query has finished. */
+int bfs_server_drain(bfs_server *s);
+
+/* Stop the worker thread and release the server (graphs stay valid). */
+int bfs_server_destroy(bfs_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFSMI_BFS_H */

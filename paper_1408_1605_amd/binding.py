@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libbfsmi.so (include/bfs.h).
+
+Every function keeps the C name and only marshals arguments: device buffers
+are torch tensors on the GPU (their data_ptr() is passed), streams are
+torch.cuda streams (their cuda_stream handle is the hipStream_t).  All
+search work runs in the library's HIP kernels; nothing here computes.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbfsmi.so")
+
+BFS_OK = 0
+BFS_PENDING = 1
+BFS_ERR_INVALID = -1
+BFS_ERR_NO_DEVICE = -2
+BFS_ERR_HIP = -3
+BFS_ERR_WORKSPACE = -4
+BFS_ERR_DEPTH = -5
+BFS_ERR_BUSY = -6
+BFS_ERR_BUDGET = -7
+BFS_ERR_TICKET = -8
+
+BFS_VALIDATE_CSR = 0x1
+BFS_WS_BATCH = 0x2
+
+BFS_OPT_EDGES_PER_THREAD = 1
+BFS_OPT_FRONTIER_MODE = 2
+BFS_OPT_LOOP_DRIVER = 3
+BFS_OPT_BATCH_TILE = 4
+BFS_OPT_GRID_WGS = 5
+
+# Every symbol include/bfs.h declares.
+EXPORTS = (
+    "bfs_last_error", "bfs_version", "bfs_workspace_bytes", "bfs_graph_create",
+    "bfs_graph_destroy", "bfs_set_option", "bfs_get_option", "bfs_run", "bfs_run_batch",
+    "bfs_server_create", "bfs_server_add_graph", "bfs_submit", "bfs_poll", "bfs_server_drain",
+    "bfs_server_destroy",
+)
+
+
+class BFSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("bfs error %d: %s" % (code, msg))
+        self.code = code
+
+
+class bfs_stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("bitmap_levels", ctypes.c_int32),
+                ("reached", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
+                ("device_ms", ctypes.c_double)]
+
+
+class bfs_server_config(ctypes.Structure):
+    _fields_ = [("max_lanes", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("level_budget_us", ctypes.c_int64)]
+
+
+class bfs_timing(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("lanes_in_batch", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbfsmi.so and declare the C signatures.  Raises if it is not
+    built (run __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libbfsmi.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sz = ctypes.c_size_t
+    sig = {
+        "bfs_last_error": (ctypes.c_char_p, []),
+        "bfs_version": (ctypes.c_int, []),
+        "bfs_workspace_bytes": (ctypes.c_int, [i32, i64, u32, ctypes.POINTER(sz)]),
+        "bfs_graph_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, i64, vp, vp, vp, sz, u32, vp]),
+        "bfs_graph_destroy": (ctypes.c_int, [vp]),
+        "bfs_set_option": (ctypes.c_int, [vp, ctypes.c_int, i64]),
+        "bfs_get_option": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64)]),
+        "bfs_run": (ctypes.c_int, [vp, i32, vp, vp, vp, ctypes.POINTER(bfs_stats)]),
+        "bfs_run_batch": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, vp, vp,
+                                         ctypes.POINTER(bfs_stats)]),
+        "bfs_server_create": (ctypes.c_int, [ctypes.POINTER(vp), vp, sz,
+                                             ctypes.POINTER(bfs_server_config)]),
+        "bfs_server_add_graph": (ctypes.c_int, [vp, vp, ctypes.POINTER(i32)]),
+        "bfs_submit": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(ctypes.c_uint64)]),
+        "bfs_poll": (ctypes.c_int, [vp, ctypes.c_uint64, vp, ctypes.POINTER(bfs_timing)]),
+        "bfs_server_drain": (ctypes.c_int, [vp]),
+        "bfs_server_destroy": (ctypes.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, allow=(BFS_OK,)) -> int:
+    if code in allow:
+        return code
+    msg = load().bfs_last_error()
+    raise BFSError(code, msg.decode() if msg else "")
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream) or None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+def bfs_last_error() -> str:
+    m = load().bfs_last_error()
+    return m.decode() if m else ""
+
+
+def bfs_version() -> int:
+    return int(load().bfs_version())
+
+
+def bfs_workspace_bytes(V: int, nnz: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().bfs_workspace_bytes(V, nnz, flags, ctypes.byref(out)))
+    return int(out.value)
+
+
+def bfs_graph_create(V: int, nnz: int, d_row_offsets, d_col, d_workspace, ws_bytes: int | None = None,
+                     flags: int = 0, stream=None) -> int:
+    """Returns the opaque handle (an int).  Tensors must live on the GPU."""
+    h = ctypes.c_void_p(0)
+    if ws_bytes is None:
+        ws_bytes = d_workspace.numel() * d_workspace.element_size()
+    _check(load().bfs_graph_create(ctypes.byref(h), V, nnz, _ptr(d_row_offsets), _ptr(d_col),
+                                   _ptr(d_workspace), ws_bytes, flags, _stream(stream)))
+    return int(h.value)
+
+
+def bfs_graph_destroy(g: int) -> None:
+    _check(load().bfs_graph_destroy(g))
+
+
+def bfs_set_option(g: int, key: int, value: int) -> None:
+    _check(load().bfs_set_option(g, key, value))
+
+
+def bfs_get_option(g: int, key: int) -> int:
+    v = ctypes.c_int64(0)
+    _check(load().bfs_get_option(g, key, ctypes.byref(v)))
+    return int(v.value)
+
+
+def bfs_run(g: int, root: int, d_levels, d_parents=None, stream=None) -> bfs_stats:
+    st = bfs_stats()
+    _check(load().bfs_run(g, root, _ptr(d_levels), _ptr(d_parents), _stream(stream),
+                          ctypes.byref(st)))
+    return st
+
+
+def bfs_run_batch(g: int, roots, d_levels, stream=None) -> bfs_stats:
+    roots = [int(r) for r in roots]
+    arr = (ctypes.c_int32 * max(len(roots), 1))(*roots)
+    st = bfs_stats()
+    _check(load().bfs_run_batch(g, arr, len(roots), _ptr(d_levels), _stream(stream),
+                                ctypes.byref(st)))
+    return st
+
+
+def bfs_server_create(d_arena, arena_bytes: int | None = None, max_lanes: int = 64,
+                      max_inflight: int = 8) -> int:
+    h = ctypes.c_void_p(0)
+    if arena_bytes is None:
+        arena_bytes = d_arena.numel() * d_arena.element_size()
+    cfg = bfs_server_config(max_lanes, max_inflight, 0)
+    _check(load().bfs_server_create(ctypes.byref(h), _ptr(d_arena), arena_bytes,
+                                    ctypes.byref(cfg)))
+    return int(h.value)
+
+
+def bfs_server_add_graph(s: int, g: int) -> int:
+    gid = ctypes.c_int32(-1)
+    _check(load().bfs_server_add_graph(s, g, ctypes.byref(gid)))
+    return int(gid.value)
+
+
+def bfs_submit(s: int, graph_id: int, root: int) -> int:
+    t = ctypes.c_uint64(0)
+    _check(load().bfs_submit(s, graph_id, root, ctypes.byref(t)))
+    return int(t.value)
+
+
+def bfs_poll(s: int, ticket: int, dst_levels=None):
+    """dst_levels: a host numpy int32[V] array or None.  Returns
+    (status, bfs_timing) with status BFS_OK or BFS_PENDING."""
+    tm = bfs_timing()
+    ptr = None if dst_levels is None else dst_levels.ctypes.data
+    code = _check(load().bfs_poll(s, ticket, ptr, ctypes.byref(tm)), allow=(BFS_OK, BFS_PENDING))
+    return code, tm
+
+
+def bfs_server_drain(s: int) -> None:
+    _check(load().bfs_server_drain(s))
+
+
+def bfs_server_destroy(s: int) -> None:
+    _check(load().bfs_server_destroy(s))
+
+
+# ---------------------------------------------------------------------------
+# Convenience: device-resident graph built from host CSR arrays.
+
+
+@dataclass
+class Graph:
+    """A CSR graph resident in device memory plus its library handle.
+    Owns the torch tensors it allocates (offsets, columns, workspace)."""
+    V: int
+    nnz: int
+    off: object
+    col: object
+    ws: object
+    handle: int
+
+    @classmethod
+    def from_csr(cls, off, col, flags: int = 0, device: str = "cuda", stream=None) -> "Graph":
+        import numpy as np
+        import torch
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        V = int(off.shape[0] - 1)
+        nnz = int(off[-1])
+        d_off = torch.from_numpy(off).to(device)
+        d_col = torch.from_numpy(col if col.size else np.zeros(1, np.int32)).to(device)
+        nbytes = bfs_workspace_bytes(V, nnz, flags)
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        torch.cuda.synchronize()
+        h = bfs_graph_create(V, nnz, d_off, d_col, ws, nbytes, flags, stream)
+        return cls(V, nnz, d_off, d_col, ws, h)
+
+    def run(self, root: int, levels=None, parents=None, want_parents: bool = True, stream=None):
+        import torch
+        if levels is None:
+            levels = torch.empty(self.V, dtype=torch.int32, device=self.off.device)
+        if parents is None and want_parents:
+            parents = torch.empty(self.V, dtype=torch.int32, device=self.off.device)
+        st = bfs_run(self.handle, root, levels, parents, stream)
+        return levels, parents, st
+
+    def run_batch(self, roots, levels=None, stream=None):
+        import torch
+        if levels is None:
+            levels = torch.empty((len(roots), self.V), dtype=torch.int8, device=self.off.device)
+        st = bfs_run_batch(self.handle, roots, levels, stream)
+        return levels, st
+
+    def set_option(self, key: int, value: int) -> None:
+        bfs_set_option(self.handle, key, value)
+
+    def close(self) -> None:
+        if self.handle:
+            bfs_graph_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,362 @@
+// C ABI: errors, workspace layout, graph handles and the single-root search
+// driver (host-driven level loop, one 64-byte control read-back per level).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "runtime.h"
+
+namespace bfsmi {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(BFS_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+int ok()
+{
+    g_err[0] = 0;
+    return BFS_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
+{
+    WsLayout L{};
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p = align_up(p + bytes, 256);
+        return at;
+    };
+    const size_t W = ((size_t)V + 31) / 32;
+    const size_t nblk = ((size_t)V + kScanChunk - 1) / kScanChunk;
+    const size_t ntile_max = (size_t)((nnz + kMinTile - 1) / kMinTile);
+    L.vis = take(W * 4);
+    L.vis_old = take(W * 4);
+    L.q0 = take((size_t)V * 4);
+    L.q1 = take((size_t)V * 4);
+    L.deg = take((size_t)V * 4);
+    L.cumul = take(((size_t)V + 1) * 8);
+    L.bsum = take((nblk + 1) * 8);
+    L.tile_k = take((ntile_max + 2) * 4);
+    L.ctrl = take(sizeof(Ctrl));
+    L.scratch = take(256);
+    if (flags & BFS_WS_BATCH) {
+        L.ms_seen = take((size_t)V * 8);
+        L.ms_front = take((size_t)V * 8);
+        L.ms_next = take((size_t)V * 8);
+        L.ms_ctrl = take(sizeof(MsCtrl));
+    }
+    L.total = p;
+    return L;
+}
+
+}  // namespace bfsmi
+
+using namespace bfsmi;
+
+extern "C" {
+
+const char* bfs_last_error(void) { return g_err; }
+
+int bfs_version(void) { return 100; }
+
+int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t* bytes)
+{
+    if (!bytes) return fail(BFS_ERR_INVALID, "bytes is NULL");
+    if (V < 1) return fail(BFS_ERR_INVALID, "V must be >= 1 (got %d)", V);
+    if (nnz < 0 || nnz > ((int64_t)1 << 62)) return fail(BFS_ERR_INVALID, "nnz out of range");
+    if (flags & ~(BFS_VALIDATE_CSR | BFS_WS_BATCH)) return fail(BFS_ERR_INVALID, "unknown flags");
+    *bytes = ws_layout(V, nnz, flags).total;
+    return ok();
+}
+
+int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_row_offsets,
+                     const int32_t* d_col, void* d_workspace, size_t ws_bytes, uint32_t flags,
+                     void* hip_stream)
+{
+    if (!out) return fail(BFS_ERR_INVALID, "graph out-pointer is NULL");
+    *out = nullptr;
+    if (V < 1) return fail(BFS_ERR_INVALID, "V must be >= 1 (got %d)", V);
+    if (nnz < 0 || nnz > ((int64_t)1 << 62)) return fail(BFS_ERR_INVALID, "nnz out of range");
+    if (!d_row_offsets) return fail(BFS_ERR_INVALID, "row offsets pointer is NULL");
+    if (!d_col && nnz > 0) return fail(BFS_ERR_INVALID, "column pointer is NULL");
+    if (!d_workspace) return fail(BFS_ERR_INVALID, "workspace pointer is NULL");
+    if ((uintptr_t)d_workspace % 256 != 0) return fail(BFS_ERR_INVALID, "workspace not 256-byte aligned");
+    if (flags & ~(BFS_VALIDATE_CSR | BFS_WS_BATCH)) return fail(BFS_ERR_INVALID, "unknown flags");
+    const WsLayout L = ws_layout(V, nnz, flags);
+    if (ws_bytes < L.total)
+        return fail(BFS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(BFS_ERR_NO_DEVICE, "no HIP device");
+    int dev = 0;
+    BFS_HIP_TRY(hipGetDevice(&dev));
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, d_workspace) == hipSuccess && attr.type == hipMemoryTypeDevice)
+        dev = attr.device;
+    (void)hipGetLastError();
+
+    bfs_graph* g = new (std::nothrow) bfs_graph();
+    if (!g) return fail(BFS_ERR_INVALID, "out of host memory");
+    g->V = V;
+    g->nnz = nnz;
+    g->W = (int32_t)(((int64_t)V + 31) / 32);
+    g->off = d_row_offsets;
+    g->col = d_col;
+    g->ws = static_cast<char*>(d_workspace);
+    g->ws_bytes = ws_bytes;
+    g->flags = flags;
+    g->device = dev;
+    g->L = L;
+    g->vis = reinterpret_cast<uint32_t*>(g->ws + L.vis);
+    g->vis_old = reinterpret_cast<uint32_t*>(g->ws + L.vis_old);
+    g->q[0] = reinterpret_cast<int32_t*>(g->ws + L.q0);
+    g->q[1] = reinterpret_cast<int32_t*>(g->ws + L.q1);
+    g->deg = reinterpret_cast<int32_t*>(g->ws + L.deg);
+    g->cumul = reinterpret_cast<int64_t*>(g->ws + L.cumul);
+    g->bsum = reinterpret_cast<int64_t*>(g->ws + L.bsum);
+    g->tile_k = reinterpret_cast<int32_t*>(g->ws + L.tile_k);
+    g->ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ctrl);
+    g->scratch = reinterpret_cast<int32_t*>(g->ws + L.scratch);
+    if (flags & BFS_WS_BATCH) {
+        g->ms_seen = reinterpret_cast<uint64_t*>(g->ws + L.ms_seen);
+        g->ms_front = reinterpret_cast<uint64_t*>(g->ws + L.ms_front);
+        g->ms_next = reinterpret_cast<uint64_t*>(g->ws + L.ms_next);
+        g->ms_ctrl = reinterpret_cast<MsCtrl*>(g->ws + L.ms_ctrl);
+    }
+
+    auto cleanup = [&](int code) {
+        bfs_graph_destroy(g);
+        return code;
+    };
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(dev) != hipSuccess) return cleanup(fail(BFS_ERR_HIP, "hipSetDevice failed"));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return cleanup(fail(BFS_ERR_HIP, "hipGetDeviceProperties failed"));
+    }
+    g->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+
+    hipError_t e = hipHostMalloc((void**)&g->h_ctrl, sizeof(Ctrl) + sizeof(MsCtrl) + 256,
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return cleanup(hip_fail(e, "hipHostMalloc"));
+    }
+    g->h_ms_ctrl = reinterpret_cast<MsCtrl*>(reinterpret_cast<char*>(g->h_ctrl) + sizeof(Ctrl));
+    if ((e = hipEventCreate(&g->ev0)) != hipSuccess || (e = hipEventCreate(&g->ev1)) != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return cleanup(hip_fail(e, "hipEventCreate"));
+    }
+
+    // CSR checks (always computes the maximum degree; BFS_VALIDATE_CSR adds
+    // the column-range check).
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int32_t* dflags = g->scratch;  // [0] bad bits, [1] max degree
+    int32_t h[2] = {0, 0};
+    e = hipMemcpyAsync(dflags, h, sizeof(h), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_validate_csr(s, V, nnz, d_row_offsets, d_col, dflags, dflags + 1,
+                                1 /* column ids are always checked: a bad id would fault */);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, dflags, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "CSR check"));
+    if (h[0] & 3) return cleanup(fail(BFS_ERR_INVALID, "row offsets are not a valid CSR (code %d)", h[0]));
+    if (h[0] & 4) return cleanup(fail(BFS_ERR_INVALID, "a column id is outside [0, V)"));
+    g->maxdeg = h[1];
+    *out = g;
+    return ok();
+}
+
+int bfs_graph_destroy(bfs_graph* g)
+{
+    if (!g) return ok();
+    if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    delete g;
+    return ok();
+}
+
+int bfs_set_option(bfs_graph* g, int key, int64_t value)
+{
+    if (!g) return fail(BFS_ERR_INVALID, "graph is NULL");
+    switch (key) {
+    case BFS_OPT_EDGES_PER_THREAD:
+        if (value != 1 && value != 2 && value != 4 && value != 8)
+            return fail(BFS_ERR_INVALID, "edges per thread must be 1, 2, 4 or 8");
+        g->ept = (int)value;
+        break;
+    case BFS_OPT_FRONTIER_MODE:
+        if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "frontier mode must be 0..2");
+        g->frontier_mode = (int)value;
+        break;
+    case BFS_OPT_LOOP_DRIVER:
+        if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "loop driver must be 0..2");
+        g->loop_driver = (int)value;
+        break;
+    case BFS_OPT_BATCH_TILE:
+        if (value != 256 && value != 512 && value != 1024 && value != 2048)
+            return fail(BFS_ERR_INVALID, "batch tile must be 256, 512, 1024 or 2048");
+        g->batch_tile = (int)value;
+        break;
+    case BFS_OPT_GRID_WGS:
+        if (value < 1 || value > 64) return fail(BFS_ERR_INVALID, "grid workgroups per CU must be 1..64");
+        g->grid_wgs = (int)value;
+        break;
+    default:
+        return fail(BFS_ERR_INVALID, "unknown option %d", key);
+    }
+    return ok();
+}
+
+int bfs_get_option(bfs_graph* g, int key, int64_t* value)
+{
+    if (!g || !value) return fail(BFS_ERR_INVALID, "NULL argument");
+    switch (key) {
+    case BFS_OPT_EDGES_PER_THREAD: *value = g->ept; break;
+    case BFS_OPT_FRONTIER_MODE: *value = g->frontier_mode; break;
+    case BFS_OPT_LOOP_DRIVER: *value = g->loop_driver; break;
+    case BFS_OPT_BATCH_TILE: *value = g->batch_tile; break;
+    case BFS_OPT_GRID_WGS: *value = g->grid_wgs; break;
+    default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
+    }
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BusyGuard {
+    bfs_graph* g;
+    bool held;
+    explicit BusyGuard(bfs_graph* gg) : g(gg), held(false)
+    {
+        int expect = 0;
+        held = g->busy.compare_exchange_strong(expect, 1);
+    }
+    ~BusyGuard()
+    {
+        if (held) g->busy.store(0);
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+namespace bfsmi {
+
+// The host-driven level loop for one root.
+static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
+                         hipStream_t s, bfs_stats* st)
+{
+    const int tile = kWG * g->ept;
+    const int64_t T = ((int64_t)g->V + 31) / 32;  // list longer than the bitmap
+    const int allow_bitmap = g->frontier_mode == 1 ? 0 : (g->frontier_mode == 2 ? 2 : 1);
+    const int grid_cap = g->num_cus * g->grid_wgs;
+    // tile_k holds ceil(nnz / kMinTile) + 2 entries; ntiles + 1 must fit
+    const int64_t tile_cap = (g->nnz + kMinTile - 1) / kMinTile + 1;
+
+    BFS_HIP_TRY(hipEventRecord(g->ev0, s));
+    BFS_HIP_TRY(launch_init(s, g->V, g->W, root, levels, parents, g->vis, g->vis_old, g->q[0],
+                            g->ctrl, grid_cap));
+    int32_t qlen = 1;
+    int32_t lvl = 1;
+    int cur = 0;
+    int64_t reached = 1, edges = 0;
+    int32_t nlevels = 1, bitmap_levels = 0;
+    while (true) {
+        const int32_t* Q = g->q[cur];
+        int32_t* Qn = g->q[cur ^ 1];
+        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->off, g->deg, g->bsum, g->cumul, g->tile_k,
+                                tile_cap, tile, T, allow_bitmap, g->ctrl));
+        int64_t rmax = (int64_t)qlen * (int64_t)g->maxdeg;
+        if (rmax > g->nnz) rmax = g->nnz;
+        const int64_t tiles_ub = (rmax + tile - 1) / tile;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_ub, grid_cap));
+        BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, Q, g->cumul, g->tile_k, g->off, g->col, g->vis,
+                                  g->vis_old, levels, parents, lvl, Qn, g->ctrl));
+        const bool maybe_bitmap = (allow_bitmap == 2 && rmax > 0) || (allow_bitmap == 1 && rmax > T);
+        if (maybe_bitmap) {
+            const int64_t nb = ((int64_t)g->W + kBitmapWordsPerWG - 1) / kBitmapWordsPerWG;
+            const int grid2 = (int)std::max<int64_t>(1, std::min<int64_t>(nb, grid_cap));
+            BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->vis, g->vis_old, Qn, levels,
+                                               lvl, g->ctrl));
+        }
+        BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        BFS_HIP_TRY(hipStreamSynchronize(s));
+        if (g->h_ctrl->err)
+            return fail(BFS_ERR_HIP, "internal guard tripped (code %d)", g->h_ctrl->err);
+        edges += g->h_ctrl->r;
+        const uint32_t qn = g->h_ctrl->qn_count;
+        if (qn == 0) break;
+        if (g->h_ctrl->bitmap_out) bitmap_levels++;
+        reached += qn;
+        nlevels++;
+        qlen = (int32_t)qn;
+        cur ^= 1;
+        lvl++;
+    }
+    BFS_HIP_TRY(hipEventRecord(g->ev1, s));
+    BFS_HIP_TRY(hipEventSynchronize(g->ev1));
+    if (st) {
+        float ms = 0.f;
+        BFS_HIP_TRY(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+        st->levels = nlevels;
+        st->bitmap_levels = bitmap_levels;
+        st->reached = reached;
+        st->edges_scanned = edges;
+        st->device_ms = ms;
+    }
+    return ok();
+}
+
+}  // namespace bfsmi
+
+extern "C" int bfs_run(bfs_graph* g, int32_t root, int32_t* d_levels, int32_t* d_parents,
+                       void* hip_stream, bfs_stats* st)
+{
+    if (!g) return fail(BFS_ERR_INVALID, "graph is NULL");
+    if (root < 0 || root >= g->V) return fail(BFS_ERR_INVALID, "root %d outside [0, %d)", root, g->V);
+    if (!d_levels) return fail(BFS_ERR_INVALID, "levels pointer is NULL");
+    BusyGuard busy(g);
+    if (!busy.held) return fail(BFS_ERR_BUSY, "graph handle is in use");
+    DeviceGuard dg(g->device);
+    return run_host_loop(g, root, d_levels, d_parents, static_cast<hipStream_t>(hip_stream), st);
+}

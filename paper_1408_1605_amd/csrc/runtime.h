@@ -1,0 +1,73 @@
+// Host-side runtime structures behind the C ABI.
+#pragma once
+
+#include <atomic>
+#include <string>
+
+#include "../../include/bfs.h"
+#include "bfs_internal.h"
+
+namespace bfsmi {
+
+// Record a message for bfs_last_error() and return the status code.
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int ok();
+
+#define BFS_HIP_TRY(expr)                                  \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return ::bfsmi::hip_fail(_e, #expr); \
+    } while (0)
+
+// Carving of the caller's workspace.  Every region is 256-byte aligned.
+struct WsLayout {
+    size_t vis, vis_old, q0, q1, deg, cumul, bsum, tile_k, ctrl, scratch;
+    size_t ms_seen, ms_front, ms_next, ms_ctrl;
+    size_t total;
+};
+WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags);
+
+}  // namespace bfsmi
+
+struct bfs_graph {
+    int32_t V = 0;
+    int64_t nnz = 0;
+    int32_t W = 0;  // bitmap words
+    const int64_t* off = nullptr;
+    const int32_t* col = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t flags = 0;
+    int device = 0;
+    int num_cus = 0;
+    int32_t maxdeg = 0;
+    bfsmi::WsLayout L{};
+
+    uint32_t* vis = nullptr;
+    uint32_t* vis_old = nullptr;
+    int32_t* q[2] = {nullptr, nullptr};
+    int32_t* deg = nullptr;
+    int64_t* cumul = nullptr;
+    int64_t* bsum = nullptr;
+    int32_t* tile_k = nullptr;
+    bfsmi::Ctrl* ctrl = nullptr;
+    int32_t* scratch = nullptr;  // small device scratch (create-time checks)
+    uint64_t* ms_seen = nullptr;
+    uint64_t* ms_front = nullptr;
+    uint64_t* ms_next = nullptr;
+    bfsmi::MsCtrl* ms_ctrl = nullptr;
+
+    bfsmi::Ctrl* h_ctrl = nullptr;      // pinned host mirror
+    bfsmi::MsCtrl* h_ms_ctrl = nullptr; // pinned host mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // options
+    int ept = 4;
+    int frontier_mode = 0;  // 0 auto, 1 list only, 2 bitmap whenever possible
+    int loop_driver = 0;    // 0 auto, 1 host, 2 device loop for small frontiers
+    int batch_tile = 1024;
+    int grid_wgs = 8;
+
+    std::atomic<int> busy{0};
+};

@@ -1,0 +1,190 @@
+"""GPU parity of the single-root search against the CPU oracle.
+
+Levels must match the oracle bit-exactly; parents (not unique under atomic
+races) must pass the oracle's tree validator; per-level frontier sizes must
+equal the oracle's (each vertex claimed exactly once).  Everything goes
+through the C ABI (libbfsmi.so) via the ctypes binding.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bfsmi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1408_1605_amd as p
+    p.load()
+    return p
+
+
+def check(p, g, G, root, mode=0, ept=4, want_parents=True, directed=False):
+    _say("case", g.name, "V=%d nnz=%d root=%d mode=%d ept=%d" % (g.V, g.nnz, root, mode, ept))
+    G.set_option(p.BFS_OPT_FRONTIER_MODE, mode)
+    G.set_option(p.BFS_OPT_EDGES_PER_THREAD, ept)
+    lv, pa, st = G.run(root, want_parents=want_parents)
+    torch.cuda.synchronize()
+    lv = lv.cpu().numpy()
+    ref = oracle.bfs(g.off, g.col, root)
+    assert np.array_equal(lv, ref.level), "levels differ at %s" % np.nonzero(lv != ref.level)[0][:10]
+    assert st.levels == ref.nlevels
+    assert st.reached == ref.reached
+    assert st.edges_scanned == ref.edges_scanned
+    if want_parents:
+        pa = pa.cpu().numpy()
+        code, bad = oracle.validate(g.off, g.col, root, lv, pa, directed=directed)
+        assert code == 0, (oracle.INVARIANTS[code], bad)
+    return st
+
+
+def test_duplicates_and_self_loops(bfsmi):
+    g = graphgen.from_edges(6, [0, 0, 0, 1, 1, 2, 3, 4], [1, 1, 0, 1, 2, 3, 4, 5])
+    G = bfsmi.Graph.from_csr(g.off, g.col)
+    for r in range(6):
+        check(bfsmi, g, G, r)
+
+
+def test_path_and_disconnected(bfsmi):
+    n = 2000
+    src = np.concatenate([np.arange(999), np.arange(1000, 1999)])
+    g = graphgen.from_edges(n, src, src + 1)
+    G = bfsmi.Graph.from_csr(g.off, g.col)
+    for root in (0, 500, 1500, 1999):
+        check(bfsmi, g, G, root)
+
+
+@pytest.fixture(scope="module")
+def rmat16(bfsmi):
+    g = graphgen.rmat(16)
+    return g, bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_VALIDATE_CSR)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("ept", [1, 2, 4, 8])
+def test_rmat16_modes_ept(bfsmi, rmat16, mode, ept):
+    g, G = rmat16
+    roots = graphgen.pick_roots(g, 4, graphgen.root_seed(16))
+    for r in roots:
+        check(bfsmi, g, G, int(r), mode=mode, ept=ept)
+
+
+def test_rmat16_sixteen_roots_auto(bfsmi, rmat16):
+    g, G = rmat16
+    roots = graphgen.pick_roots(g, 16, graphgen.root_seed(16))
+    nb = 0
+    for r in roots:
+        st = check(bfsmi, g, G, int(r))
+        nb += st.bitmap_levels
+    assert nb > 0  # R-MAT frontiers cross T = V/32 at their peak
+
+
+def test_isolated_root(bfsmi, rmat16):
+    g, G = rmat16
+    iso = int(np.nonzero(np.diff(g.off) == 0)[0][0])
+    st = check(bfsmi, g, G, iso)
+    assert st.levels == 1 and st.reached == 1
+
+
+def test_no_parents(bfsmi, rmat16):
+    g, G = rmat16
+    r = int(graphgen.pick_roots(g, 1, 5)[0])
+    check(bfsmi, g, G, r, want_parents=False)
+
+
+def test_repeatable(bfsmi, rmat16):
+    g, G = rmat16
+    r = int(graphgen.pick_roots(g, 1, 9)[0])
+    outs = [G.run(r)[0].cpu().numpy() for _ in range(5)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 300), (37, 23), (128, 128)])
+def test_grids_manhattan(bfsmi, w, h):
+    g = graphgen.grid(w, h)
+    G = bfsmi.Graph.from_csr(g.off, g.col)
+    r_, c_ = np.divmod(np.arange(g.V), w)
+    for root in sorted({0, g.V - 1, (h // 2) * w + w // 2}):
+        check(bfsmi, g, G, root)
+        lv = G.run(root)[0].cpu().numpy()
+        r0, c0 = divmod(root, w)
+        assert np.array_equal(lv, np.abs(r_ - r0) + np.abs(c_ - c0))
+
+
+def test_hub_star(bfsmi):
+    # one vertex of degree 200k: a single frontier entry spans many tiles
+    n = 200_001
+    g = graphgen.from_edges(n, np.zeros(n - 1, np.int64), np.arange(1, n))
+    G = bfsmi.Graph.from_csr(g.off, g.col)
+    for ept in (1, 8):
+        check(bfsmi, g, G, 0, ept=ept)
+        check(bfsmi, g, G, 77, ept=ept)
+
+
+def test_directed_zero_outdegree(bfsmi):
+    """Directed graph where most frontier vertices have no out-edges: the
+    tile's entry range exceeds the tile, exercising the global search."""
+    rng = np.random.default_rng(3)
+    n = 50_000
+    # vertex 0 points to every other vertex; only 1% of them point onwards
+    src = [np.zeros(n - 1, np.int64)]
+    dst = [np.arange(1, n)]
+    movers = rng.choice(np.arange(1, n), size=500, replace=False)
+    src.append(movers)
+    dst.append(rng.integers(1, n, size=500))
+    g = graphgen.from_edges(n, np.concatenate(src), np.concatenate(dst), symmetric=False)
+    G = bfsmi.Graph.from_csr(g.off, g.col)
+    for mode in (0, 1, 2):
+        check(bfsmi, g, G, 0, mode=mode, directed=True)
+        check(bfsmi, g, G, int(movers[0]), mode=mode, directed=True)
+
+
+def test_bad_arguments_on_gpu(bfsmi, rmat16):
+    g, G = rmat16
+    lv = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.bfs_run(G.handle, g.V, lv)
+    assert e.value.code == bfsmi.BFS_ERR_INVALID
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.bfs_run(G.handle, -1, lv)
+    assert e.value.code == bfsmi.BFS_ERR_INVALID
+    # workspace too small
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.bfs_graph_create(g.V, g.nnz, G.off, G.col, ws, 1024)
+    assert e.value.code == bfsmi.BFS_ERR_WORKSPACE
+    # an out-of-range column id is rejected at creation
+    bad = g.col.copy()
+    bad[17] = g.V + 5
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.Graph.from_csr(g.off, bad)
+    assert e.value.code == bfsmi.BFS_ERR_INVALID
+    # non-monotone offsets
+    off = g.off.copy()
+    off[10] = off[11] + 1
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.Graph.from_csr(off, g.col)
+    assert e.value.code == bfsmi.BFS_ERR_INVALID
+
+
+@pytest.mark.skipif(os.environ.get("BFSMI_BIG", "1") == "0", reason="large graphs disabled")
+def test_rmat20_parity(bfsmi):
+    g = graphgen.rmat(20)
+    G = bfsmi.Graph.from_csr(g.off, g.col)
+    for r in graphgen.pick_roots(g, 3, graphgen.root_seed(20)):
+        check(bfsmi, g, G, int(r))
