@@ -57,6 +57,10 @@ extern "C" {
 /* Flags for bfs_workspace_bytes / bfs_graph_create. */
 #define BFS_VALIDATE_CSR  0x1u /* check offsets and column ids on creation    */
 #define BFS_WS_BATCH      0x2u /* also reserve the multi-source batch arrays  */
+#define BFS_DEGREE_ORDER  0x4u /* search on a degree-ordered internal copy of
+                                  the CSR (built on the GPU at creation, kept
+                                  in the workspace: + 16 V + 4 nnz bytes);
+                                  results are still in the caller's ids     */
 
 /* Options for bfs_set_option (tuning knobs; defaults are sensible). */
 #define BFS_OPT_EDGES_PER_THREAD 1 /* 1, 2, 4 or 8 frontier edges per thread    */
@@ -67,6 +71,14 @@ extern "C" {
 #define BFS_OPT_BATCH_TILE       4 /* edges per workgroup in the batch kernels:
                                       256, 512, 1024 or 2048                  */
 #define BFS_OPT_GRID_WGS         5 /* workgroups per CU for grid-stride kernels */
+#define BFS_OPT_PROFILE          6 /* 1: time each kernel class with HIP events
+                                      (fills the *_ms fields of bfs_stats)    */
+#define BFS_OPT_VISITED_SUMMARY  7 /* before heavy levels, summarise the visited
+                                      bitmap so the expansion's early visited
+                                      test skips most bitmap loads:
+                                      0 off, 1 (default) fully visited id
+                                      prefix, 2 prefix + one LDS bit per fully
+                                      visited block of ids                    */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;
@@ -77,6 +89,15 @@ typedef struct bfs_stats {
     int64_t reached;        /* vertices reached (sum of frontier sizes)         */
     int64_t edges_scanned;  /* sum of out-degrees of reached vertices           */
     double  device_ms;      /* stream time of the call (HIP events)             */
+    /* With BFS_OPT_PROFILE: summed stream time of each kernel class. */
+    double  init_ms, scan_ms, expand_ms, compact_ms;
+    int32_t expand_launches;
+    int32_t device_loop_levels; /* levels run inside the device-side loop      */
+    /* Algorithmic bytes of the expansion kernels: per level
+     * 4 * edges (column stream) + 20 * frontier entries (queue entry, its
+     * cumulative degree, its row offset) + 4 per discovered vertex for its
+     * parent + 8 per discovered vertex in list mode (queue slot, level).   */
+    int64_t expand_bytes;
 } bfs_stats;
 
 /* Thread-local message of the last failing call ("" if none). */

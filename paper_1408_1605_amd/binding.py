@@ -28,12 +28,15 @@ BFS_ERR_TICKET = -8
 
 BFS_VALIDATE_CSR = 0x1
 BFS_WS_BATCH = 0x2
+BFS_DEGREE_ORDER = 0x4
 
 BFS_OPT_EDGES_PER_THREAD = 1
 BFS_OPT_FRONTIER_MODE = 2
 BFS_OPT_LOOP_DRIVER = 3
 BFS_OPT_BATCH_TILE = 4
 BFS_OPT_GRID_WGS = 5
+BFS_OPT_PROFILE = 6
+BFS_OPT_VISITED_SUMMARY = 7
 
 # Every symbol include/bfs.h declares.
 EXPORTS = (
@@ -53,7 +56,10 @@ class BFSError(RuntimeError):
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("bitmap_levels", ctypes.c_int32),
                 ("reached", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
-                ("device_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("init_ms", ctypes.c_double),
+                ("scan_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
+                ("compact_ms", ctypes.c_double), ("expand_launches", ctypes.c_int32),
+                ("device_loop_levels", ctypes.c_int32), ("expand_bytes", ctypes.c_int64)]
 
 
 class bfs_server_config(ctypes.Structure):

@@ -59,11 +59,20 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
     L.tile_k = take((ntile_max + 2) * 4);
     L.ctrl = take(sizeof(Ctrl));
     L.scratch = take(256);
+    L.summary = take(kSummaryMaxWords * 4);
     if (flags & BFS_WS_BATCH) {
         L.ms_seen = take((size_t)V * 8);
         L.ms_front = take((size_t)V * 8);
         L.ms_next = take((size_t)V * 8);
-        L.ms_ctrl = take(sizeof(MsCtrl));
+        L.ms_ctrl = take(sizeof(Ctrl));
+        L.ms_roots = take(64 * 4);
+    }
+    if (flags & BFS_DEGREE_ORDER) {
+        L.rank = take((size_t)V * 4);
+        L.orig = take((size_t)V * 4);
+        L.off_r = take(((size_t)V + 1) * 8);
+        L.col_r = take((size_t)(nnz > 0 ? nnz : 1) * 4);
+        L.hist = take(2 * 4096 * 4);
     }
     L.total = p;
     return L;
@@ -84,7 +93,8 @@ int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t* bytes)
     if (!bytes) return fail(BFS_ERR_INVALID, "bytes is NULL");
     if (V < 1) return fail(BFS_ERR_INVALID, "V must be >= 1 (got %d)", V);
     if (nnz < 0 || nnz > ((int64_t)1 << 62)) return fail(BFS_ERR_INVALID, "nnz out of range");
-    if (flags & ~(BFS_VALIDATE_CSR | BFS_WS_BATCH)) return fail(BFS_ERR_INVALID, "unknown flags");
+    if (flags & ~(BFS_VALIDATE_CSR | BFS_WS_BATCH | BFS_DEGREE_ORDER))
+        return fail(BFS_ERR_INVALID, "unknown flags");
     *bytes = ws_layout(V, nnz, flags).total;
     return ok();
 }
@@ -101,7 +111,8 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     if (!d_col && nnz > 0) return fail(BFS_ERR_INVALID, "column pointer is NULL");
     if (!d_workspace) return fail(BFS_ERR_INVALID, "workspace pointer is NULL");
     if ((uintptr_t)d_workspace % 256 != 0) return fail(BFS_ERR_INVALID, "workspace not 256-byte aligned");
-    if (flags & ~(BFS_VALIDATE_CSR | BFS_WS_BATCH)) return fail(BFS_ERR_INVALID, "unknown flags");
+    if (flags & ~(BFS_VALIDATE_CSR | BFS_WS_BATCH | BFS_DEGREE_ORDER))
+        return fail(BFS_ERR_INVALID, "unknown flags");
     const WsLayout L = ws_layout(V, nnz, flags);
     if (ws_bytes < L.total)
         return fail(BFS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
@@ -138,11 +149,29 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     g->tile_k = reinterpret_cast<int32_t*>(g->ws + L.tile_k);
     g->ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ctrl);
     g->scratch = reinterpret_cast<int32_t*>(g->ws + L.scratch);
+    g->summary = reinterpret_cast<uint32_t*>(g->ws + L.summary);
+    {
+        // blocks of 2^shift ids, at most kSummaryMaxWords * 32 of them
+        int shift = 10;
+        while ((((int64_t)V + (1ll << shift) - 1) >> shift) > (int64_t)kSummaryMaxWords * 32) ++shift;
+        g->summary_shift = shift;
+        g->summary_blocks = (int32_t)(((int64_t)V + (1ll << shift) - 1) >> shift);
+        g->summary_words = (g->summary_blocks + 31) / 32;
+    }
+    g->s_off = d_row_offsets;
+    g->s_col = d_col;
+    if (flags & BFS_DEGREE_ORDER) {
+        g->rank = reinterpret_cast<int32_t*>(g->ws + L.rank);
+        g->orig = reinterpret_cast<int32_t*>(g->ws + L.orig);
+        g->s_off = reinterpret_cast<int64_t*>(g->ws + L.off_r);
+        g->s_col = reinterpret_cast<int32_t*>(g->ws + L.col_r);
+    }
     if (flags & BFS_WS_BATCH) {
         g->ms_seen = reinterpret_cast<uint64_t*>(g->ws + L.ms_seen);
         g->ms_front = reinterpret_cast<uint64_t*>(g->ws + L.ms_front);
         g->ms_next = reinterpret_cast<uint64_t*>(g->ws + L.ms_next);
-        g->ms_ctrl = reinterpret_cast<MsCtrl*>(g->ws + L.ms_ctrl);
+        g->ms_ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ms_ctrl);
+        g->ms_roots = reinterpret_cast<int32_t*>(g->ws + L.ms_roots);
     }
 
     auto cleanup = [&](int code) {
@@ -159,16 +188,24 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     }
     g->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
 
-    hipError_t e = hipHostMalloc((void**)&g->h_ctrl, sizeof(Ctrl) + sizeof(MsCtrl) + 256,
+    // pinned host block: [Ctrl][Ctrl for the batch][64 batch roots]
+    hipError_t e = hipHostMalloc((void**)&g->h_ctrl, 2 * sizeof(Ctrl) + 64 * sizeof(int32_t),
                                  hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipSetDevice(prev);
         return cleanup(hip_fail(e, "hipHostMalloc"));
     }
-    g->h_ms_ctrl = reinterpret_cast<MsCtrl*>(reinterpret_cast<char*>(g->h_ctrl) + sizeof(Ctrl));
+    g->h_ms_ctrl = g->h_ctrl + 1;
+    g->h_roots = reinterpret_cast<int32_t*>(g->h_ctrl + 2);
     if ((e = hipEventCreate(&g->ev0)) != hipSuccess || (e = hipEventCreate(&g->ev1)) != hipSuccess) {
         (void)hipSetDevice(prev);
         return cleanup(hip_fail(e, "hipEventCreate"));
+    }
+    for (int i = 0; i < 4; ++i) {
+        if ((e = hipEventCreate(&g->pev[i])) != hipSuccess) {
+            (void)hipSetDevice(prev);
+            return cleanup(hip_fail(e, "hipEventCreate"));
+        }
     }
 
     // CSR checks (always computes the maximum degree; BFS_VALIDATE_CSR adds
@@ -182,11 +219,33 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
                                 1 /* column ids are always checked: a bad id would fault */);
     if (e == hipSuccess) e = hipMemcpyAsync(h, dflags, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipSetDevice(prev);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "CSR check"));
-    if (h[0] & 3) return cleanup(fail(BFS_ERR_INVALID, "row offsets are not a valid CSR (code %d)", h[0]));
-    if (h[0] & 4) return cleanup(fail(BFS_ERR_INVALID, "a column id is outside [0, V)"));
+    if (e != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return cleanup(hip_fail(e, "CSR check"));
+    }
+    if (h[0] & 3) {
+        (void)hipSetDevice(prev);
+        return cleanup(fail(BFS_ERR_INVALID, "row offsets are not a valid CSR (code %d)", h[0]));
+    }
+    if (h[0] & 4) {
+        (void)hipSetDevice(prev);
+        return cleanup(fail(BFS_ERR_INVALID, "a column id is outside [0, V)"));
+    }
     g->maxdeg = h[1];
+    if (flags & BFS_DEGREE_ORDER) {
+        const int64_t tile_cap = (nnz + kMinTile - 1) / kMinTile + 1;
+        e = build_degree_order(s, V, nnz, d_row_offsets, d_col, g->rank, g->orig,
+                               const_cast<int64_t*>(g->s_off), const_cast<int32_t*>(g->s_col),
+                               g->deg, g->bsum, g->tile_k, tile_cap,
+                               reinterpret_cast<uint32_t*>(g->ws + L.hist), g->ctrl,
+                               g->num_cus * 8);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipSetDevice(prev);
+            return cleanup(hip_fail(e, "degree ordering"));
+        }
+    }
+    (void)hipSetDevice(prev);
     *out = g;
     return ok();
 }
@@ -194,9 +253,13 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
 int bfs_graph_destroy(bfs_graph* g)
 {
     if (!g) return ok();
+    if (g->ms_graph) (void)hipGraphExecDestroy(g->ms_graph);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
+    for (int i = 0; i < 4; ++i)
+        if (g->pev[i]) (void)hipEventDestroy(g->pev[i]);
     delete g;
     return ok();
 }
@@ -227,6 +290,14 @@ int bfs_set_option(bfs_graph* g, int key, int64_t value)
         if (value < 1 || value > 64) return fail(BFS_ERR_INVALID, "grid workgroups per CU must be 1..64");
         g->grid_wgs = (int)value;
         break;
+    case BFS_OPT_PROFILE:
+        if (value < 0 || value > 1) return fail(BFS_ERR_INVALID, "profile must be 0 or 1");
+        g->profile = (int)value;
+        break;
+    case BFS_OPT_VISITED_SUMMARY:
+        if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "visited summary must be 0, 1 or 2");
+        g->use_summary = (int)value;
+        break;
     default:
         return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
@@ -242,6 +313,8 @@ int bfs_get_option(bfs_graph* g, int key, int64_t* value)
     case BFS_OPT_LOOP_DRIVER: *value = g->loop_driver; break;
     case BFS_OPT_BATCH_TILE: *value = g->batch_tile; break;
     case BFS_OPT_GRID_WGS: *value = g->grid_wgs; break;
+    case BFS_OPT_PROFILE: *value = g->profile; break;
+    case BFS_OPT_VISITED_SUMMARY: *value = g->use_summary; break;
     default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
     return ok();
@@ -282,6 +355,13 @@ struct DeviceGuard {
 
 namespace bfsmi {
 
+static float event_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
+    return ms;
+}
+
 // The host-driven level loop for one root.
 static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
                          hipStream_t s, bfs_stats* st)
@@ -292,41 +372,78 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
     const int grid_cap = g->num_cus * g->grid_wgs;
     // tile_k holds ceil(nnz / kMinTile) + 2 entries; ntiles + 1 must fit
     const int64_t tile_cap = (g->nnz + kMinTile - 1) / kMinTile + 1;
+    const bool prof = g->profile != 0;
+    bfs_stats acc{};
 
     BFS_HIP_TRY(hipEventRecord(g->ev0, s));
-    BFS_HIP_TRY(launch_init(s, g->V, g->W, root, levels, parents, g->vis, g->vis_old, g->q[0],
-                            g->ctrl, grid_cap));
+    BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, levels, parents, g->vis, g->vis_old,
+                            g->q[0], g->ctrl, grid_cap));
+    const int32_t sum_words = g->summary_words;
+    const int xgrid_full = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, 0));
+    const int xgrid_sum = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, sum_words));
+    if (prof) {
+        BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
+        BFS_HIP_TRY(hipEventSynchronize(g->pev[0]));
+        acc.init_ms = event_ms(g->ev0, g->pev[0]);
+    }
     int32_t qlen = 1;
     int32_t lvl = 1;
     int cur = 0;
-    int64_t reached = 1, edges = 0;
-    int32_t nlevels = 1, bitmap_levels = 0;
+    int64_t reached = 1, edges = 0, xbytes = 0;
+    int32_t nlevels = 1, bitmap_levels = 0, xlaunches = 0;
     while (true) {
         const int32_t* Q = g->q[cur];
         int32_t* Qn = g->q[cur ^ 1];
-        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->off, g->deg, g->bsum, g->cumul, g->tile_k,
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
+        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->deg, g->bsum, g->cumul, g->tile_k,
                                 tile_cap, tile, T, allow_bitmap, g->ctrl));
         int64_t rmax = (int64_t)qlen * (int64_t)g->maxdeg;
         if (rmax > g->nnz) rmax = g->nnz;
         const int64_t tiles_ub = (rmax + tile - 1) / tile;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_ub, grid_cap));
-        BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, Q, g->cumul, g->tile_k, g->off, g->col, g->vis,
-                                  g->vis_old, levels, parents, lvl, Qn, g->ctrl));
+        // heavy levels get the visited summary (a cheap pass over the bitmap):
+        // the fully visited prefix always, the LDS block bits in mode 2
+        const bool use_sum = g->use_summary > 0 && rmax > T;
+        const bool lds_sum = use_sum && g->use_summary == 2;
+        const int grid = (int)std::max<int64_t>(
+            1, std::min<int64_t>(tiles_ub, lds_sum ? xgrid_sum : xgrid_full));
+        if (use_sum) {
+            const int64_t nthr = (int64_t)g->summary_blocks << (g->summary_shift - 7);
+            const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(grid_cap, (nthr + kWG - 1) / kWG));
+            BFS_HIP_TRY(launch_visited_summary(s, gs, g->V, g->W, g->vis, g->summary_shift,
+                                               g->summary_blocks, g->summary, g->ctrl));
+        }
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
+        BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, Q, g->cumul, g->tile_k, g->s_off,
+                                  g->s_col, g->orig, g->summary, lds_sum ? sum_words : 0,
+                                  g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, levels,
+                                  parents, lvl, Qn, g->ctrl));
+        xlaunches++;
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[2], s));
         const bool maybe_bitmap = (allow_bitmap == 2 && rmax > 0) || (allow_bitmap == 1 && rmax > T);
         if (maybe_bitmap) {
             const int64_t nb = ((int64_t)g->W + kBitmapWordsPerWG - 1) / kBitmapWordsPerWG;
             const int grid2 = (int)std::max<int64_t>(1, std::min<int64_t>(nb, grid_cap));
-            BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->vis, g->vis_old, Qn, levels,
-                                               lvl, g->ctrl));
+            BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->orig, g->vis, g->vis_old,
+                                               Qn, levels, lvl, g->ctrl));
         }
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
         BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
         BFS_HIP_TRY(hipStreamSynchronize(s));
         if (g->h_ctrl->err)
             return fail(BFS_ERR_HIP, "internal guard tripped (code %d)", g->h_ctrl->err);
-        edges += g->h_ctrl->r;
+        if (prof) {
+            acc.scan_ms += event_ms(g->pev[0], g->pev[1]);
+            acc.expand_ms += event_ms(g->pev[1], g->pev[2]);
+            acc.compact_ms += event_ms(g->pev[2], g->pev[3]);
+        }
+        const int64_t r = g->h_ctrl->r;
         const uint32_t qn = g->h_ctrl->qn_count;
+        const bool bm = g->h_ctrl->bitmap_out != 0;
+        edges += r;
+        xbytes += 4 * r + 20 * (int64_t)qlen + (parents ? 4 : 0) * (int64_t)qn +
+                  (bm ? 0 : 8 * (int64_t)qn);
         if (qn == 0) break;
-        if (g->h_ctrl->bitmap_out) bitmap_levels++;
+        if (bm) bitmap_levels++;
         reached += qn;
         nlevels++;
         qlen = (int32_t)qn;
@@ -336,13 +453,14 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
     BFS_HIP_TRY(hipEventRecord(g->ev1, s));
     BFS_HIP_TRY(hipEventSynchronize(g->ev1));
     if (st) {
-        float ms = 0.f;
-        BFS_HIP_TRY(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+        *st = acc;
         st->levels = nlevels;
         st->bitmap_levels = bitmap_levels;
         st->reached = reached;
         st->edges_scanned = edges;
-        st->device_ms = ms;
+        st->device_ms = event_ms(g->ev0, g->ev1);
+        st->expand_launches = xlaunches;
+        st->expand_bytes = xbytes;
     }
     return ok();
 }

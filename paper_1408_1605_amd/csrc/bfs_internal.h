@@ -12,6 +12,7 @@ constexpr int kScanChunk = kWG * kScanItems;
 constexpr int kBitmapWordsPerWG = kWG; // words per workgroup in bitmap->list
 constexpr int kMaxEPT = 8;
 constexpr int kMinTile = kWG;         // smallest edge tile (EPT = 1)
+constexpr int kSummaryMaxWords = 2048; // visited summary: <= 8 KB of LDS
 
 // Per-level control block in device memory.  The host reads it back once
 // per level; the kernels read the fields they need directly.
@@ -28,39 +29,86 @@ struct alignas(64) Ctrl {
     int32_t levels;      // device loop: levels completed
     int32_t bitmap_levels;
     int32_t err;         // set when a guard trips (never expected)
-    int32_t pad[3];
-};
-
-// Multi-source batch control block.
-struct alignas(64) MsCtrl {
-    int64_t r;
-    int32_t ntiles;
-    uint32_t qn_count;     // union frontier size of the next level
-    uint64_t alive;        // OR of new bits found in this level (lanes alive)
-    int32_t overflow;      // a level exceeded the output type
-    int32_t pad[7];
+    int32_t full_prefix; // every id below it is visited (visited summary)
+    int32_t overflow;    // batch: a level did not fit the output type
+    int32_t pad;
+    uint64_t alive;      // batch: OR of the lanes that found vertices this level
+    uint64_t last_alive; // batch: alive of the last completed level
+    int8_t* out8;        // batch: output rows (read by the device each launch)
 };
 
 // ---- single-root kernels (frontier.hip) ----
 hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root,
-                       int32_t* level, int32_t* parent, uint32_t* vis,
-                       uint32_t* vis_old, int32_t* Q, Ctrl* ctrl, int grid_cap);
+                       const int32_t* rank, int32_t* level, int32_t* parent,
+                       uint32_t* vis, uint32_t* vis_old, int32_t* Q, Ctrl* ctrl,
+                       int grid_cap);
 
 hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen,
                        const int64_t* off, int32_t* deg, int64_t* bsum,
                        int64_t* cumul, int32_t* tile_k, int64_t tile_cap, int tile,
                        int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl);
 
+// Same scan with the frontier size taken from ctrl->qlen (fixed grid,
+// grid-stride); every kernel returns at once when ctrl->done is set.
+hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int64_t* off,
+                           int32_t* deg, int64_t* bsum, int64_t* cumul, int32_t* tile_k,
+                           int64_t tile_cap, int tile, Ctrl* ctrl);
+
 hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int32_t* Q,
                          const int64_t* cumul, const int32_t* tile_k,
-                         const int64_t* off, const int32_t* col, uint32_t* vis,
-                         uint32_t* vis_old, int32_t* level, int32_t* parent,
-                         int32_t lvl, int32_t* Qn, Ctrl* ctrl);
+                         const int64_t* off, const int32_t* col, const int32_t* orig,
+                         const uint32_t* summary, int32_t summary_words, int32_t shift,
+                         int use_prefix, uint32_t* vis, uint32_t* vis_old, int32_t* level,
+                         int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl);
+
+// Visited summary before a heavy level: ctrl->full_prefix and one bit per
+// block of 2^shift ids (set when the whole block is visited).
+hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
+                                  const uint32_t* vis, int32_t shift, int32_t nblocks,
+                                  uint32_t* summary, Ctrl* ctrl);
+
+// Resident expansion workgroups per CU for this configuration.
+int expand_blocks_per_cu(int ept, int summary_words);
 
 hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
-                                  uint32_t* vis, uint32_t* vis_old,
-                                  int32_t* Qn, int32_t* level, int32_t lvl,
-                                  Ctrl* ctrl);
+                                  const int32_t* orig, uint32_t* vis, uint32_t* vis_old,
+                                  int32_t* Qn, int32_t* level, int32_t lvl, Ctrl* ctrl);
+
+// Degree-ordered internal relabelling (relabel.hip).  rank[v] is v's
+// internal id (vertices in non-increasing degree order, ties arbitrary),
+// orig[rank[v]] = v; off_r / col_r is the CSR in internal ids (row x is
+// the row of orig[x], neighbours mapped through rank).
+// ---- multi-source batch (msbfs.hip) ----
+// Lanes are bits of a 64-bit mask per vertex: seen (reached), front (this
+// level's frontier), next (found during this level).  All launches read
+// their sizes from ctrl and return at once when ctrl->done is set.
+hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* h_roots_dev,
+                          int32_t n_roots, const int32_t* rank, uint64_t* seen, uint64_t* front,
+                          uint64_t* next, int8_t* out8, int32_t* Q, Ctrl* ctrl);
+hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid,
+                           int ept, int32_t V, int64_t tile_cap, const int64_t* off,
+                           const int32_t* col, const int32_t* orig, const int32_t* Q,
+                           int32_t* Qn, int32_t* deg, int64_t* bsum, int64_t* cumul,
+                           int32_t* tile_k, uint64_t* seen, uint64_t* front, uint64_t* next,
+                           int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl);
+int ms_expand_blocks_per_cu(int ept);
+
+// Serving lanes (msbfs.hip).  lane_out: device table of 64 int16 result
+// pointers; lane_start: device int32[64]; join: device int32 pairs
+// (root, lane).
+hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t* front,
+                            uint64_t* next, Ctrl* ctrl);
+hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t mask);
+hipError_t launch_fill16(hipStream_t s, int grid, int16_t* p, int64_t n, int16_t val);
+hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32_t* join,
+                           const int32_t* rank, uint64_t* seen, uint64_t* front,
+                           int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl);
+
+hipError_t build_degree_order(hipStream_t s, int32_t V, int64_t nnz, const int64_t* off,
+                              const int32_t* col, int32_t* rank, int32_t* orig,
+                              int64_t* off_r, int32_t* col_r, int32_t* deg_tmp,
+                              int64_t* bsum_tmp, int32_t* tile_k, int64_t tile_cap,
+                              uint32_t* hist_tmp, Ctrl* ctrl, int grid_cap);
 
 hipError_t launch_validate_csr(hipStream_t s, int32_t V, int64_t nnz,
                                const int64_t* off, const int32_t* col,

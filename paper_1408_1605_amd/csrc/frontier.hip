@@ -8,64 +8,23 @@
 //            v = col[off[Q[k]] + e - cumul[k]]; v's bit in the visited bitmap
 //            is probed with a plain load and claimed with atomicOr; the
 //            thread whose returned word lacked the bit is the only winner
-//            and sets parent[v] = Q[k] (and level[v] in list mode)
-//            (Algorithm 3)                                    (k_expand)
+//            and sets level[v] and parent[v] = Q[k]  (Algorithm 3)  (k_expand)
 //   next   : list mode: winners append to the next queue (one atomicAdd per
 //            wave); bitmap mode: the next frontier is the set of bits that
-//            turned on during the level, compacted to a vertex-ordered list
-//            that also sets level[v] with coalesced stores
+//            turned on during the level, compacted to an id-ordered list
 //            (Section 5)                                      (k_bitmap_to_queue)
 #include "bfs_internal.h"
+#include "tile_map.h"
+#include "wave_ops.h"
 
 namespace bfsmi {
-
-// Number of set bits of mask in lanes below the calling lane.
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T x)
-{
-    const int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const T y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
-
-// Exclusive scan over the 256 threads of a workgroup; *total receives the
-// sum.  s_wave must hold kWG / 64 elements.  Contains two barriers: every
-// thread of the workgroup must call it.
-template <typename T>
-__device__ __forceinline__ T wg_exclusive_scan(T x, T* total, T* s_wave)
-{
-    const int lane = __lane_id();
-    const int wave = threadIdx.x >> 6;
-    const T incl = wave_inclusive_scan(x);
-    if (lane == 63) s_wave[wave] = incl;
-    __syncthreads();
-    T before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kWG / 64; ++w) {
-        const T t = s_wave[w];
-        if (w < wave) before += t;
-        tot += t;
-    }
-    __syncthreads();
-    *total = tot;
-    return before + incl - x;
-}
 
 // ---------------------------------------------------------------------------
 // Initialisation (Algorithm 2): level = -1, parent = -1, bitmap = 0, then the
 // root: level 0, parent = root, its visited bit, frontier = {root}.
 
 __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root,
+                                              const int32_t* __restrict__ rank,
                                               int32_t* __restrict__ level,
                                               int32_t* __restrict__ parent,
                                               uint32_t* __restrict__ vis,
@@ -101,15 +60,16 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
         level[v] = v == root ? 0 : -1;
         if (parent) parent[v] = v == root ? root : -1;
     }
-    const int64_t rw = root >> 5;
-    const uint32_t rb = 1u << (root & 31);
+    const int32_t rin = rank ? rank[root] : root;  // the root's internal id
+    const int64_t rw = rin >> 5;
+    const uint32_t rb = 1u << (rin & 31);
     for (int64_t i = tid; i < W; i += stride) {
         const uint32_t w = i == rw ? rb : 0u;
         vis[i] = w;
         vis_old[i] = w;
     }
     if (tid == 0) {
-        Q[0] = root;
+        Q[0] = rin;
         ctrl->r = 0;
         ctrl->ntiles = 0;
         ctrl->bitmap_out = 0;
@@ -125,9 +85,9 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
     }
 }
 
-hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, int32_t* level,
-                       int32_t* parent, uint32_t* vis, uint32_t* vis_old, int32_t* Q,
-                       Ctrl* ctrl, int grid_cap)
+hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, const int32_t* rank,
+                       int32_t* level, int32_t* parent, uint32_t* vis, uint32_t* vis_old,
+                       int32_t* Q, Ctrl* ctrl, int grid_cap)
 {
     const bool vec = ((uintptr_t)level % 16 == 0) &&
                      (parent == nullptr || (uintptr_t)parent % 16 == 0);
@@ -136,8 +96,8 @@ hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, int32_
     int64_t grid = (work + kWG - 1) / kWG;
     if (grid > grid_cap) grid = grid_cap;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(kWG), 0, s, V, W, root, level, parent,
-                       vis, vis_old, Q, ctrl, vec ? 1 : 0);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(kWG), 0, s, V, W, root, rank, level,
+                       parent, vis, vis_old, Q, ctrl, vec ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -145,37 +105,51 @@ hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, int32_
 // Degree scan: deg, block sums, scan of block sums, per-entry cumul and
 // tile heads (tile_k[t] = frontier entry holding edge t * tile).
 
-__global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__ Q, int32_t qlen,
+// With dev != 0 the frontier size comes from ctrl->qlen and the kernels
+// return at once when ctrl->done is set, so a fixed-size launch sequence can
+// be replayed for any level (device-driven loops, graph capture); the block
+// loops are grid-stride in both modes.
+
+__global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__ Q, int32_t qlen_arg,
                                                      const int64_t* __restrict__ off,
                                                      int32_t* __restrict__ deg,
-                                                     int64_t* __restrict__ bsum)
+                                                     int64_t* __restrict__ bsum,
+                                                     const Ctrl* __restrict__ ctrl, int dev)
 {
     __shared__ int64_t s_wave[kWG / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-    int64_t sum = 0;
+    if (dev && ctrl->done) return;
+    const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
+    const int64_t nblk = ((int64_t)qlen + kScanChunk - 1) / kScanChunk;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t base = blk * kScanChunk;
+        int64_t sum = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t k = base + j * kWG + threadIdx.x;
-        if (k < qlen) {
-            const int32_t u = Q[k];
-            const int64_t d = off[u + 1] - off[u];
-            deg[k] = (int32_t)d;
-            sum += d;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t k = base + j * kWG + threadIdx.x;
+            if (k < qlen) {
+                const int32_t u = Q[k];
+                const int64_t d = off[u + 1] - off[u];
+                deg[k] = (int32_t)d;
+                sum += d;
+            }
         }
+        int64_t tot;
+        wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
+        if (threadIdx.x == 0) bsum[blk] = tot;
     }
-    int64_t tot;
-    wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, int32_t nblk,
-                                                  int32_t qlen, int64_t tile_cap, int32_t tile,
+__global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, int32_t qlen_arg,
+                                                  int64_t tile_cap, int32_t tile,
                                                   int64_t bitmap_threshold, int allow_bitmap,
                                                   int64_t* __restrict__ cumul,
                                                   int32_t* __restrict__ tile_k,
-                                                  Ctrl* __restrict__ ctrl)
+                                                  Ctrl* __restrict__ ctrl, int dev)
 {
     __shared__ int64_t s_wave[kWG / 64];
+    if (dev && ctrl->done) return;
+    const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
+    const int32_t nblk = (int32_t)(((int64_t)qlen + kScanChunk - 1) / kScanChunk);
     int64_t carry = 0;
     for (int32_t b0 = 0; b0 < nblk; b0 += kWG) {
         const int32_t b = b0 + threadIdx.x;
@@ -199,54 +173,63 @@ __global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, in
         ctrl->qlen = qlen;
         ctrl->bitmap_out = (allow_bitmap == 2 && r > 0) || (allow_bitmap == 1 && r > bitmap_threshold);
         ctrl->qn_count = 0;
+        ctrl->full_prefix = 0x7fffffff;
+        ctrl->r_total += r;
         cumul[qlen] = r;
         tile_k[ntiles] = qlen - 1;
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ deg, int32_t qlen,
+__global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ deg, int32_t qlen_arg,
                                                    const int64_t* __restrict__ bsum,
                                                    int64_t tile_cap,
                                                    int32_t tile, int64_t* __restrict__ cumul,
-                                                   int32_t* __restrict__ tile_k)
+                                                   int32_t* __restrict__ tile_k,
+                                                   const Ctrl* __restrict__ ctrl, int dev)
 {
     __shared__ int64_t s_wave[kWG / 64];
     // +1 word of padding every 8 entries keeps the strided reads conflict-light
     __shared__ int32_t s_deg[kScanChunk + kScanChunk / kScanItems];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    if (dev && ctrl->done) return;
+    const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
+    const int64_t nblk = ((int64_t)qlen + kScanChunk - 1) / kScanChunk;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t base = blk * kScanChunk;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int32_t li = j * kWG + threadIdx.x;
-        const int64_t k = base + li;
-        s_deg[li + li / kScanItems] = k < qlen ? deg[k] : 0;
-    }
-    __syncthreads();
-    int64_t local[kScanItems];
-    int64_t sum = 0;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int32_t li = j * kWG + threadIdx.x;
+            const int64_t k = base + li;
+            s_deg[li + li / kScanItems] = k < qlen ? deg[k] : 0;
+        }
+        __syncthreads();
+        int64_t local[kScanItems];
+        int64_t sum = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int32_t li = threadIdx.x * kScanItems + j;
-        local[j] = sum;
-        sum += s_deg[li + li / kScanItems];
-    }
-    int64_t tot;
-    const int64_t ex = wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
-    const int64_t start = bsum[blockIdx.x] + ex;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int32_t li = threadIdx.x * kScanItems + j;
+            local[j] = sum;
+            sum += s_deg[li + li / kScanItems];
+        }
+        int64_t tot;
+        const int64_t ex = wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
+        const int64_t start = bsum[blk] + ex;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int32_t li = threadIdx.x * kScanItems + j;
-        const int64_t k = base + li;
-        if (k < qlen) {
-            const int64_t c = start + local[j];
-            cumul[k] = c;
-            const int32_t d = s_deg[li + li / kScanItems];
-            if (d > 0) {
-                const int64_t t0 = (c + tile - 1) / tile;
-                int64_t t1 = (c + d - 1) / tile;
-                if (t1 >= tile_cap) t1 = tile_cap - 1;
-                for (int64_t t = t0; t <= t1; ++t) tile_k[t] = (int32_t)k;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int32_t li = threadIdx.x * kScanItems + j;
+            const int64_t k = base + li;
+            if (k < qlen) {
+                const int64_t c = start + local[j];
+                cumul[k] = c;
+                const int32_t d = s_deg[li + li / kScanItems];
+                if (d > 0) {
+                    const int64_t t0 = (c + tile - 1) / tile;
+                    int64_t t1 = (c + d - 1) / tile;
+                    if (t1 >= tile_cap) t1 = tile_cap - 1;
+                    for (int64_t t = t0; t <= t1; ++t) tile_k[t] = (int32_t)k;
+                }
             }
         }
+        __syncthreads();  // s_deg is reused by the next block
     }
 }
 
@@ -257,25 +240,111 @@ hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int6
 {
     const int32_t nblk = (int32_t)(((int64_t)qlen + kScanChunk - 1) / kScanChunk);
     if (nblk > 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kWG), 0, s, Q, qlen, off, deg, bsum);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kWG), 0, s, Q, qlen, off, deg, bsum,
+                           ctrl, 0);
     }
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, nblk, qlen, tile_cap, tile,
-                       bitmap_threshold, allow_bitmap, cumul, tile_k, ctrl);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, qlen, tile_cap, tile,
+                       bitmap_threshold, allow_bitmap, cumul, tile_k, ctrl, 0);
     if (nblk > 0) {
         hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kWG), 0, s, deg, qlen, bsum, tile_cap,
-                           tile, cumul, tile_k);
+                           tile, cumul, tile_k, ctrl, 0);
     }
     return hipGetLastError();
 }
 
+hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int64_t* off,
+                           int32_t* deg, int64_t* bsum, int64_t* cumul, int32_t* tile_k,
+                           int64_t tile_cap, int tile, Ctrl* ctrl)
+{
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(kWG), 0, s, Q, 0, off, deg, bsum, ctrl, 1);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, 0, tile_cap, tile,
+                       (int64_t)1 << 62, 0, cumul, tile_k, ctrl, 1);
+    hipLaunchKernelGGL(k_scan_down, dim3(grid), dim3(kWG), 0, s, deg, 0, bsum, tile_cap, tile,
+                       cumul, tile_k, ctrl, 1);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// Frontier expansion.  A workgroup owns a tile of TILE = 256 * EPT
-// consecutive frontier edges [e0, e0 + TILE).  The frontier entries that
-// overlap the tile, [tile_k[t], tile_k[t + 1]], are staged in LDS; each
-// thread binary-searches the staged cumulative degrees once for its first
-// slot and advances linearly over EPT consecutive slots (Section 3.4.1),
-// recording slot -> entry in LDS.  The edges are then visited with a slot
-// stride of 256 so that the column loads of a wave are contiguous.
+// Visited summary for the expansion's early test (a two-level bitmap).
+//
+// Before a heavy level, k_visited_summary records (a) full_prefix: every
+// vertex id below it is already visited, and (b) one bit per block of
+// 2^shift ids that is set when the whole block is visited.  Both only ever
+// under-report (bits are only set during a search), so "summary says
+// visited" implies the bitmap bit is set and the paper's early test would
+// return.  With degree-ordered ids the highest-degree vertices, which most
+// frontier edges point to, fill the lowest ids, and at the heaviest level
+// most probes are answered by a register compare or an LDS bit.
+
+__global__ __launch_bounds__(kWG) void k_visited_summary(int32_t V, int32_t W,
+                                                         const uint32_t* __restrict__ vis,
+                                                         int32_t shift, int32_t nblocks,
+                                                         uint32_t* __restrict__ summary,
+                                                         Ctrl* __restrict__ ctrl)
+{
+    // Thread t checks words 4t .. 4t+3 (ids 128t .. 128t+127).  A block of
+    // 2^shift ids (shift >= 10) spans G = 2^(shift-7) >= 8 threads; the
+    // summary starts all-ones and the first lane of each block's group clears
+    // the block's bit when the group saw an open (unvisited) id.
+    const int32_t G = 1 << (shift - 7);
+    const int g = G < 64 ? G : 64;
+    const int64_t nthreads = (int64_t)nblocks * G;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    const int lane = __lane_id();
+    for (int64_t t0 = (int64_t)blockIdx.x * kWG; t0 < nthreads; t0 += stride) {
+        const int64_t t = t0 + threadIdx.x;
+        uint32_t any_open = 0;
+        int32_t first_open = 0x7fffffff;
+        if (t < nthreads) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t w = t * 4 + j;
+                const uint32_t x = w < W ? vis[w] : 0u;
+                const int64_t lo = w * 32;
+                uint32_t valid = 0xffffffffu;  // ids at or beyond V count as visited
+                if (lo + 32 > V) valid = lo >= V ? 0u : ((1u << (V - lo)) - 1u);
+                const uint32_t open = ~x & valid;
+                if (open && !any_open) first_open = (int32_t)(lo + __builtin_ctz(open));
+                any_open |= open ? 1u : 0u;
+            }
+        }
+        uint32_t grp = any_open;
+        for (int d = 1; d < g; d <<= 1) grp |= __shfl_xor(grp, d, 64);
+        if (t < nthreads && (lane % g) == 0 && grp) {
+            const int64_t b = t / G;
+            atomicAnd(&summary[b >> 5], ~(1u << (b & 31)));
+        }
+        int32_t m = first_open;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t o = __shfl_xor(m, d, 64);
+            m = o < m ? o : m;
+        }
+        if (lane == 0 && m != 0x7fffffff) atomicMin(&ctrl->full_prefix, m);
+    }
+}
+
+hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
+                                  const uint32_t* vis, int32_t shift, int32_t nblocks,
+                                  uint32_t* summary, Ctrl* ctrl)
+{
+    if (grid < 1) grid = 1;
+    // bits start set ("full") and are cleared for blocks with an open id
+    hipError_t e = hipMemsetAsync(summary, 0xff, ((size_t)nblocks + 31) / 32 * 4, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_visited_summary, dim3(grid), dim3(kWG), 0, s, V, W, vis, shift, nblocks,
+                       summary, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Frontier expansion (Algorithm 3).  Edge slots come from map_tile (the
+// cumulative-degree search of Section 3.4, one search per EPT edges).
+//
+// Vertex ids inside the search may be internal (degree-ordered) ids: then
+// orig maps an internal id to the caller's id for the level / parent
+// outputs.  When summary_words > 0, the visited summary of this level is
+// copied into LDS and answers the early test before any bitmap load.
 
 template <int EPT>
 __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __restrict__ Q,
@@ -283,6 +352,10 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
                                                 const int32_t* __restrict__ tile_k,
                                                 const int64_t* __restrict__ off,
                                                 const int32_t* __restrict__ col,
+                                                const int32_t* __restrict__ orig,
+                                                const uint32_t* __restrict__ summary,
+                                                int32_t summary_words, int32_t shift,
+                                                int use_prefix,
                                                 uint32_t* __restrict__ vis,
                                                 uint32_t* __restrict__ vis_old,
                                                 int32_t* __restrict__ level,
@@ -290,97 +363,37 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
                                                 int32_t* __restrict__ Qn,
                                                 Ctrl* __restrict__ ctrl)
 {
-    constexpr int TILE = kWG * EPT;
-    __shared__ int32_t s_cum[TILE + 1];
-    __shared__ int32_t s_u[TILE + 1];
-    __shared__ int64_t s_base[TILE + 1];
-    __shared__ uint16_t s_map[TILE];
+    __shared__ TileLds<EPT> L;
+    extern __shared__ uint32_t s_sum[];
 
     const int64_t r = ctrl->r;
     const int32_t ntiles = ctrl->ntiles;
     const bool list_out = ctrl->bitmap_out == 0;
+    const int32_t skip_below = use_prefix ? ctrl->full_prefix : 0;
+    if ((int32_t)blockIdx.x >= ntiles) return;  // whole workgroup: uniform
+
+    for (int32_t w = threadIdx.x; w < summary_words; w += kWG) s_sum[w] = summary[w];
+    __syncthreads();
 
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t e0 = (int64_t)tile * TILE;
-        const int64_t rem = r - e0;
-        const int32_t n_e = rem < TILE ? (int32_t)rem : TILE;
-        const int32_t k_lo = tile_k[tile];
-        const int32_t k_hi = tile_k[tile + 1];
-        const int32_t n_k = k_hi - k_lo + 1;
-
         int32_t uu[EPT], vv[EPT];
         bool ok[EPT];
-        if (n_k <= TILE + 1) {
-            for (int32_t i = threadIdx.x; i < n_k; i += kWG) {
-                const int32_t k = k_lo + i;
-                const int32_t u = Q[k];
-                const int64_t c = cumul[k];
-                const int64_t rel = c - e0;
-                s_cum[i] = rel > 0 ? (int32_t)rel : 0;
-                s_u[i] = u;
-                s_base[i] = off[u] - c;
-            }
-            __syncthreads();
-            const int32_t s0 = threadIdx.x * EPT;
-            if (s0 < n_e) {
-                int32_t lo = 0, hi = n_k - 1;  // s_cum[0] == 0 <= s0
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (s_cum[mid] <= s0) lo = mid;
-                    else hi = mid - 1;
-                }
-                int32_t i = lo;
-#pragma unroll
-                for (int j = 0; j < EPT; ++j) {
-                    const int32_t sl = s0 + j;
-                    if (sl < n_e) {
-                        while (i + 1 < n_k && s_cum[i + 1] <= sl) ++i;
-                        s_map[sl] = (uint16_t)i;
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const int32_t sl = threadIdx.x + j * kWG;
-                ok[j] = sl < n_e;
-                uu[j] = 0;
-                vv[j] = 0;
-                if (ok[j]) {
-                    const int32_t i = s_map[sl];
-                    uu[j] = s_u[i];
-                    vv[j] = __builtin_nontemporal_load(col + (s_base[i] + e0 + sl));
-                }
-            }
-        } else {
-            // More frontier entries than tile slots (zero-degree entries):
-            // search the global cumulative array for each edge.
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const int32_t sl = threadIdx.x + j * kWG;
-                ok[j] = sl < n_e;
-                uu[j] = 0;
-                vv[j] = 0;
-                if (ok[j]) {
-                    const int64_t e = e0 + sl;
-                    int32_t lo = k_lo, hi = k_hi;
-                    while (lo < hi) {
-                        const int32_t mid = lo + ((hi - lo + 1) >> 1);
-                        if (cumul[mid] <= e) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    const int32_t u = Q[lo];
-                    uu[j] = u;
-                    vv[j] = col[off[u] + (e - cumul[lo])];
-                }
-            }
-        }
+        int64_t ee[EPT];
+        map_tile<EPT>(L, tile, r, Q, cumul, tile_k, off, col, orig, uu, vv, ok, ee);
 
-        // Visit: probe (plain load; a stale word only lets more threads try
-        // the atomic), then claim.
+        // Early visited test: summary (register / LDS), else a plain load of
+        // the bitmap word (a stale word only lets more threads try the atomic).
         uint32_t wd[EPT];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) wd[j] = ok[j] ? vis[vv[j] >> 5] : 0xffffffffu;
+        for (int j = 0; j < EPT; ++j) {
+            const int32_t v = vv[j];
+            bool known = !ok[j] || v < skip_below;
+            if (!known && summary_words > 0) {
+                const uint32_t b = (uint32_t)v >> shift;
+                known = (s_sum[b >> 5] >> (b & 31)) & 1u;
+            }
+            wd[j] = known ? 0xffffffffu : vis[v >> 5];
+        }
         bool win[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -391,10 +404,15 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
                 win[j] = !(old & m);
             }
         }
-        if (parent) {
+        int32_t vo[EPT];
 #pragma unroll
-            for (int j = 0; j < EPT; ++j)
-                if (win[j]) parent[vv[j]] = uu[j];
+        for (int j = 0; j < EPT; ++j) vo[j] = (win[j] && orig) ? orig[vv[j]] : vv[j];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (win[j]) {
+                level[vo[j]] = lvl;
+                if (parent) parent[vo[j]] = uu[j];
+            }
         }
         if (list_out) {
             uint64_t mask[EPT];
@@ -415,7 +433,6 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
                         const uint32_t pos = base + lanes_below(mask[j]);
                         if (pos < (uint32_t)V) Qn[pos] = v;
                         else ctrl->err = 2;
-                        level[v] = lvl;
                         atomicOr(vis_old + (v >> 5), 1u << (v & 31));
                     }
                     base += (uint32_t)__popcll(mask[j]);
@@ -427,33 +444,48 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
 }
 
 hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int32_t* Q,
-                         const int64_t* cumul,
-                         const int32_t* tile_k, const int64_t* off, const int32_t* col,
-                         uint32_t* vis, uint32_t* vis_old, int32_t* level, int32_t* parent,
-                         int32_t lvl, int32_t* Qn, Ctrl* ctrl)
+                         const int64_t* cumul, const int32_t* tile_k, const int64_t* off,
+                         const int32_t* col, const int32_t* orig, const uint32_t* summary,
+                         int32_t summary_words, int32_t shift, int use_prefix, uint32_t* vis,
+                         uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
+                         int32_t* Qn, Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
+    if (summary_words < 0 || summary == nullptr) summary_words = 0;
+    const size_t dyn = (size_t)summary_words * 4;
+#define BFS_EXPAND_CASE(E)                                                                        \
+    case E:                                                                                      \
+        hipLaunchKernelGGL(k_expand<E>, dim3(grid), dim3(kWG), dyn, s, V, Q, cumul, tile_k, off,  \
+                           col, orig, summary, summary_words, shift, use_prefix, vis, vis_old,    \
+                           level, parent,                                                        \
+                           lvl, Qn, ctrl);                                                       \
+        break;
     switch (ept) {
-    case 1:
-        hipLaunchKernelGGL(k_expand<1>, dim3(grid), dim3(kWG), 0, s, V, Q, cumul, tile_k, off, col,
-                           vis, vis_old, level, parent, lvl, Qn, ctrl);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_expand<2>, dim3(grid), dim3(kWG), 0, s, V, Q, cumul, tile_k, off, col,
-                           vis, vis_old, level, parent, lvl, Qn, ctrl);
-        break;
-    case 4:
-        hipLaunchKernelGGL(k_expand<4>, dim3(grid), dim3(kWG), 0, s, V, Q, cumul, tile_k, off, col,
-                           vis, vis_old, level, parent, lvl, Qn, ctrl);
-        break;
-    case 8:
-        hipLaunchKernelGGL(k_expand<8>, dim3(grid), dim3(kWG), 0, s, V, Q, cumul, tile_k, off, col,
-                           vis, vis_old, level, parent, lvl, Qn, ctrl);
-        break;
+        BFS_EXPAND_CASE(1)
+        BFS_EXPAND_CASE(2)
+        BFS_EXPAND_CASE(4)
+        BFS_EXPAND_CASE(8)
     default:
         return hipErrorInvalidValue;
     }
+#undef BFS_EXPAND_CASE
     return hipGetLastError();
+}
+
+int expand_blocks_per_cu(int ept, int summary_words)
+{
+    int n = 0;
+    const size_t dyn = (size_t)(summary_words > 0 ? summary_words : 0) * 4;
+    hipError_t e = hipErrorInvalidValue;
+    switch (ept) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_expand<1>, kWG, dyn); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_expand<2>, kWG, dyn); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_expand<4>, kWG, dyn); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_expand<8>, kWG, dyn); break;
+    default: break;
+    }
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
 }
 
 // ---------------------------------------------------------------------------
@@ -464,6 +496,7 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int3
 // queue stores of a wave are contiguous.
 
 __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
+                                                         const int32_t* __restrict__ orig,
                                                          uint32_t* __restrict__ vis,
                                                          uint32_t* __restrict__ vis_old,
                                                          int32_t* __restrict__ Qn,
@@ -504,7 +537,6 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
                     const uint32_t rank = s_off[local >> 5] + (uint32_t)__popc(w & ((1u << bit) - 1u));
                     if (base + rank < (uint32_t)V) Qn[base + rank] = v;
                     else ctrl->err = 3;
-                    level[v] = lvl;
                 }
             }
         }
@@ -512,13 +544,13 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
     }
 }
 
-hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
-                                  uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
-                                  Ctrl* ctrl)
+hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
+                                  const int32_t* orig, uint32_t* vis, uint32_t* vis_old,
+                                  int32_t* Qn, int32_t* level, int32_t lvl, Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid), dim3(kWG), 0, s, V, W, vis, vis_old, Qn,
-                       level, lvl, ctrl);
+    hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid), dim3(kWG), 0, s, V, W, orig, vis, vis_old,
+                       Qn, level, lvl, ctrl);
     return hipGetLastError();
 }
 

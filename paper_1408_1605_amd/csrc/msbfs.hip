@@ -1,0 +1,405 @@
+// Multi-source batch search: up to 64 independent searches in one pass.
+//
+// Lane b of a 64-bit mask per vertex belongs to root b.  seen[v] holds the
+// lanes that reached v, front[v] the lanes for which v is in this level's
+// frontier, next[v] the lanes that found v during this level.  A level is
+// the paper's frontier expansion (Section 3.4) run once over the union
+// frontier {v : front[v] != 0}: the same degree scan and edge -> thread
+// mapping, with the visited test and claim done on whole masks,
+//   next[v] |= front[u] & ~seen[v]   (64-bit atomic OR, no return value),
+// then a dense pass turns next into the new frontier (new = next & ~seen),
+// writes level L into row b of the output for every new lane b, and
+// compacts the union frontier.  Lanes never interact, so each row equals the
+// single-root search from its root.
+//
+// Every launch reads its sizes from ctrl and returns at once when
+// ctrl->done is set, so a fixed sequence of levels can be captured in a
+// hipGraph and replayed until the frontier is empty.
+#include "bfs_internal.h"
+#include "tile_map.h"
+#include "wave_ops.h"
+
+namespace bfsmi {
+
+__global__ __launch_bounds__(kWG) void k_ms_clear(int32_t V, int32_t n_roots,
+                                                  uint64_t* __restrict__ seen,
+                                                  uint64_t* __restrict__ front,
+                                                  uint64_t* __restrict__ next,
+                                                  int8_t* __restrict__ out8, int vec)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    const int64_t tid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    for (int64_t v = tid; v < V; v += stride) {
+        seen[v] = 0;
+        front[v] = 0;
+        next[v] = 0;
+    }
+    const int64_t nbytes = (int64_t)n_roots * V;
+    int64_t done = 0;
+    if (vec) {
+        int4* o4 = reinterpret_cast<int4*>(out8);
+        const int4 m1 = make_int4(-1, -1, -1, -1);
+        for (int64_t i = tid; i < nbytes / 16; i += stride) o4[i] = m1;
+        done = nbytes / 16 * 16;
+    }
+    for (int64_t i = done + tid; i < nbytes; i += stride) out8[i] = -1;
+}
+
+__global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
+                                                  const int32_t* __restrict__ roots,
+                                                  const int32_t* __restrict__ rank,
+                                                  uint64_t* __restrict__ seen,
+                                                  uint64_t* __restrict__ front,
+                                                  int8_t* __restrict__ out8,
+                                                  int32_t* __restrict__ Q,
+                                                  Ctrl* __restrict__ ctrl)
+{
+    __shared__ int32_t s_x[64];
+    __shared__ int32_t s_n;
+    const int b = threadIdx.x;
+    if (b == 0) s_n = 0;
+    if (b < n_roots) {
+        const int32_t r = roots[b];
+        s_x[b] = rank ? rank[r] : r;
+        out8[(int64_t)b * V + r] = 0;
+    }
+    __syncthreads();
+    if (b < n_roots) {
+        const int32_t x = s_x[b];
+        uint64_t lanes = 0;
+        bool first = true;
+        for (int c = 0; c < n_roots; ++c) {
+            if (s_x[c] == x) {
+                lanes |= 1ull << c;
+                if (c < b) first = false;
+            }
+        }
+        if (first) {
+            seen[x] = lanes;
+            front[x] = lanes;
+            Q[atomicAdd(&s_n, 1)] = x;
+        }
+    }
+    __syncthreads();
+    if (b == 0) {
+        ctrl->qlen = s_n;
+        ctrl->qn_count = 0;
+        ctrl->level = 1;
+        ctrl->done = 0;
+        ctrl->err = 0;
+        ctrl->overflow = 0;
+        ctrl->r = 0;
+        ctrl->ntiles = 0;
+        ctrl->r_total = 0;
+        ctrl->reached = s_n;
+        ctrl->levels = 1;
+        ctrl->alive = 0;
+        ctrl->last_alive = 0;
+        ctrl->out8 = out8;
+    }
+}
+
+hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* roots_dev,
+                          int32_t n_roots, const int32_t* rank, uint64_t* seen, uint64_t* front,
+                          uint64_t* next, int8_t* out8, int32_t* Q, Ctrl* ctrl)
+{
+    if (grid < 1) grid = 1;
+    const int vec = ((uintptr_t)out8 % 16) == 0;
+    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, n_roots, seen, front, next, out8,
+                       vec);
+    hipLaunchKernelGGL(k_ms_roots, dim3(1), dim3(64), 0, s, V, n_roots, roots_dev, rank, seen, front,
+                       out8, Q, ctrl);
+    return hipGetLastError();
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kWG) void k_ms_expand(const int32_t* __restrict__ Q,
+                                                   const int64_t* __restrict__ cumul,
+                                                   const int32_t* __restrict__ tile_k,
+                                                   const int64_t* __restrict__ off,
+                                                   const int32_t* __restrict__ col,
+                                                   const uint64_t* __restrict__ front,
+                                                   const uint64_t* __restrict__ seen,
+                                                   uint64_t* __restrict__ next,
+                                                   const Ctrl* __restrict__ ctrl)
+{
+    __shared__ TileLds<EPT> L;
+    if (ctrl->done) return;
+    const int64_t r = ctrl->r;
+    const int32_t ntiles = ctrl->ntiles;
+    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int32_t uu[EPT], vv[EPT];
+        bool ok[EPT];
+        int64_t ee[EPT];
+        map_tile<EPT>(L, tile, r, Q, cumul, tile_k, off, col, nullptr, uu, vv, ok, ee);
+        uint64_t f[EPT], sn[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) f[j] = ok[j] ? front[uu[j]] : 0ull;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) sn[j] = f[j] ? seen[vv[j]] : ~0ull;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const uint64_t nb = f[j] & ~sn[j];
+            if (nb) (void)__hip_atomic_fetch_or(next + vv[j], nb, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x)
+{
+    for (int d = 1; d < 64; d <<= 1) x |= __shfl_xor(x, d, 64);
+    return x;
+}
+
+// OUT16 = false: batch output, int8 rows ctrl->out8[b][v] = level.
+// OUT16 = true : serving output, lane b writes level - lane_start[b] into
+//                its own int16 buffer lane_out[b] (caller ids).
+template <bool OUT16>
+__global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* __restrict__ orig,
+                                                     uint64_t* __restrict__ seen,
+                                                     uint64_t* __restrict__ front,
+                                                     uint64_t* __restrict__ next,
+                                                     int32_t* __restrict__ Qn,
+                                                     int16_t* const* __restrict__ lane_out,
+                                                     const int32_t* __restrict__ lane_start,
+                                                     Ctrl* __restrict__ ctrl)
+{
+    if (ctrl->done) return;
+    const int32_t lvl = ctrl->level;
+    int8_t* __restrict__ out8 = ctrl->out8;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    uint64_t alive = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kWG; base < V; base += stride) {
+        const int64_t v = base + threadIdx.x;
+        uint64_t nw = 0;
+        if (v < V) {
+            const uint64_t n = next[v];
+            if (n) {
+                const uint64_t sv = seen[v];
+                nw = n & ~sv;
+                next[v] = 0;
+                if (nw) seen[v] = sv | nw;
+            }
+            front[v] = nw;
+        }
+        const uint64_t mask = __ballot(nw != 0);
+        if (mask) {
+            uint32_t pos = 0;
+            if (__lane_id() == 0) pos = atomicAdd(&ctrl->qn_count, (uint32_t)__popcll(mask));
+            pos = __shfl(pos, 0, 64) + lanes_below(mask);
+            if (nw) {
+                if (pos < (uint32_t)V) Qn[pos] = (int32_t)v;
+                else ctrl->err = 4;
+            }
+            const uint64_t lanes = wave_or64(nw);
+            const int64_t vo = (nw && orig) ? orig[v] : v;
+            if (OUT16) {
+                for (uint64_t m = lanes; m; m &= m - 1) {
+                    const int b = __builtin_ctzll(m);
+                    if ((nw >> b) & 1ull) {
+                        const int32_t d = lvl - lane_start[b];
+                        if (d > 32767) ctrl->overflow = 1;
+                        else lane_out[b][vo] = (int16_t)d;
+                    }
+                }
+            } else if (lvl > 127) {
+                if (nw) ctrl->overflow = 1;
+            } else {
+                for (uint64_t m = lanes; m; m &= m - 1) {
+                    const int b = __builtin_ctzll(m);
+                    if ((nw >> b) & 1ull) out8[(int64_t)b * V + vo] = (int8_t)lvl;
+                }
+            }
+            alive |= lanes;
+        }
+    }
+    if (__lane_id() == 0 && alive) atomicOr((unsigned long long*)&ctrl->alive, (unsigned long long)alive);
+}
+
+__global__ void k_ms_advance(Ctrl* __restrict__ ctrl)
+{
+    if (ctrl->done) return;
+    const uint32_t q = ctrl->qn_count;
+    ctrl->last_alive = ctrl->alive;  // lanes that found vertices this level
+    ctrl->alive = 0;
+    ctrl->reached += q;
+    ctrl->qlen = (int32_t)q;
+    ctrl->qn_count = 0;
+    if (q) ctrl->levels += 1;
+    ctrl->level += 1;
+    ctrl->done = (q == 0 || ctrl->overflow || ctrl->err) ? 1 : 0;
+}
+
+template <int EPT>
+static void ms_expand_launch(hipStream_t s, int grid, const int32_t* Q, const int64_t* cumul,
+                             const int32_t* tile_k, const int64_t* off, const int32_t* col,
+                             const uint64_t* front, const uint64_t* seen, uint64_t* next,
+                             const Ctrl* ctrl)
+{
+    hipLaunchKernelGGL(k_ms_expand<EPT>, dim3(grid), dim3(kWG), 0, s, Q, cumul, tile_k, off, col,
+                       front, seen, next, ctrl);
+}
+
+int ms_expand_blocks_per_cu(int ept)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (ept) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ms_expand<1>, kWG, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ms_expand<2>, kWG, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ms_expand<4>, kWG, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ms_expand<8>, kWG, 0); break;
+    default: break;
+    }
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid, int ept,
+                           int32_t V, int64_t tile_cap, const int64_t* off, const int32_t* col,
+                           const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
+                           int64_t* bsum, int64_t* cumul, int32_t* tile_k, uint64_t* seen,
+                           uint64_t* front, uint64_t* next, int16_t* const* lane_out,
+                           const int32_t* lane_start, Ctrl* ctrl)
+{
+    hipError_t e = launch_scan_dev(s, scan_grid, Q, off, deg, bsum, cumul, tile_k, tile_cap,
+                                   kWG * ept, ctrl);
+    if (e != hipSuccess) return e;
+    if (expand_grid < 1) expand_grid = 1;
+    switch (ept) {
+    case 1: ms_expand_launch<1>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
+    case 2: ms_expand_launch<2>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
+    case 4: ms_expand_launch<4>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
+    case 8: ms_expand_launch<8>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (fin_grid < 1) fin_grid = 1;
+    if (lane_out) {
+        hipLaunchKernelGGL(k_ms_finalize<true>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, seen,
+                           front, next, Qn, lane_out, lane_start, ctrl);
+    } else {
+        hipLaunchKernelGGL(k_ms_finalize<false>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, seen,
+                           front, next, Qn, lane_out, lane_start, ctrl);
+    }
+    hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Serving: lanes join a running batch at a level boundary and retire when a
+// level finds nothing for them.
+
+__global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, uint64_t* __restrict__ seen,
+                                                   uint64_t* __restrict__ front,
+                                                   uint64_t* __restrict__ next,
+                                                   Ctrl* __restrict__ ctrl)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < V; v += stride) {
+        seen[v] = 0;
+        front[v] = 0;
+        next[v] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->qlen = 0;
+        ctrl->qn_count = 0;
+        ctrl->level = 1;
+        ctrl->done = 1;  // nothing to expand until a lane joins
+        ctrl->err = 0;
+        ctrl->overflow = 0;
+        ctrl->r = 0;
+        ctrl->ntiles = 0;
+        ctrl->r_total = 0;
+        ctrl->reached = 0;
+        ctrl->levels = 0;
+        ctrl->alive = 0;
+        ctrl->last_alive = 0;
+        ctrl->out8 = nullptr;
+    }
+}
+
+// Clear the retired lanes' bits from every vertex's seen mask.
+__global__ __launch_bounds__(kWG) void k_srv_clear(int32_t V, uint64_t* __restrict__ seen,
+                                                   uint64_t mask)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < V; v += stride) {
+        const uint64_t x = seen[v];
+        if (x & mask) seen[v] = x & ~mask;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_fill16(int16_t* __restrict__ p, int64_t n, int16_t val)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) p[i] = val;
+}
+
+// Lane join_lane[i] starts a search from join_root[i] (caller id).  Its
+// root gets depth 0; its first expansion is the next level, so
+// lane_start = level - 1.  Roots not yet in the union frontier are appended.
+__global__ void k_srv_join(int32_t V, int32_t n_join, const int32_t* __restrict__ join,
+                           const int32_t* __restrict__ rank, uint64_t* __restrict__ seen,
+                           uint64_t* __restrict__ front, int16_t* const* __restrict__ lane_out,
+                           int32_t* __restrict__ lane_start, int32_t* __restrict__ Q,
+                           Ctrl* __restrict__ ctrl)
+{
+    // join[2 * i] = root, join[2 * i + 1] = lane; one wave, n_join <= 64
+    __shared__ int32_t s_app;
+    const int i = threadIdx.x;
+    if (i == 0) s_app = 0;
+    __syncthreads();
+    const int32_t qlen = ctrl->qlen;
+    if (i < n_join) {
+        const int32_t r = join[2 * i];
+        const int32_t b = join[2 * i + 1];
+        const int32_t x = rank ? rank[r] : r;
+        const uint64_t bit = 1ull << b;
+        atomicOr((unsigned long long*)&seen[x], (unsigned long long)bit);
+        const uint64_t old = atomicOr((unsigned long long*)&front[x], (unsigned long long)bit);
+        lane_out[b][r] = 0;
+        lane_start[b] = ctrl->level - 1;
+        if (old == 0) {
+            const int32_t pos = qlen + atomicAdd(&s_app, 1);
+            if (pos < V) Q[pos] = x;
+            else ctrl->err = 5;
+        }
+    }
+    __syncthreads();
+    if (i == 0) {
+        ctrl->qlen = qlen + s_app;
+        ctrl->done = 0;
+    }
+}
+
+hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t* front,
+                            uint64_t* next, Ctrl* ctrl)
+{
+    hipLaunchKernelGGL(k_srv_reset, dim3(grid), dim3(kWG), 0, s, V, seen, front, next, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t mask)
+{
+    hipLaunchKernelGGL(k_srv_clear, dim3(grid), dim3(kWG), 0, s, V, seen, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill16(hipStream_t s, int grid, int16_t* p, int64_t n, int16_t val)
+{
+    hipLaunchKernelGGL(k_fill16, dim3(grid), dim3(kWG), 0, s, p, n, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32_t* join,
+                           const int32_t* rank, uint64_t* seen, uint64_t* front,
+                           int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl)
+{
+    hipLaunchKernelGGL(k_srv_join, dim3(1), dim3(64), 0, s, V, n_join, join, rank, seen, front,
+                       lane_out, lane_start, Q, ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace bfsmi

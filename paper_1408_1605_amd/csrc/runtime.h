@@ -22,8 +22,9 @@ int ok();
 
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct WsLayout {
-    size_t vis, vis_old, q0, q1, deg, cumul, bsum, tile_k, ctrl, scratch;
-    size_t ms_seen, ms_front, ms_next, ms_ctrl;
+    size_t vis, vis_old, q0, q1, deg, cumul, bsum, tile_k, ctrl, scratch, summary;
+    size_t ms_seen, ms_front, ms_next, ms_ctrl, ms_roots;
+    size_t rank, orig, off_r, col_r, hist;
     size_t total;
 };
 WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags);
@@ -53,21 +54,37 @@ struct bfs_graph {
     int32_t* tile_k = nullptr;
     bfsmi::Ctrl* ctrl = nullptr;
     int32_t* scratch = nullptr;  // small device scratch (create-time checks)
+    uint32_t* summary = nullptr; // visited summary: one bit per block of ids
+    int32_t summary_shift = 10, summary_blocks = 0, summary_words = 0;
     uint64_t* ms_seen = nullptr;
     uint64_t* ms_front = nullptr;
     uint64_t* ms_next = nullptr;
-    bfsmi::MsCtrl* ms_ctrl = nullptr;
+    bfsmi::Ctrl* ms_ctrl = nullptr;
+    int32_t* ms_roots = nullptr;       // device copy of the batch roots (64)
+
+    // the CSR the search runs on: the caller's, or the degree-ordered copy
+    const int64_t* s_off = nullptr;
+    const int32_t* s_col = nullptr;
+    int32_t* rank = nullptr;  // caller id -> internal id (degree order only)
+    int32_t* orig = nullptr;  // internal id -> caller id (degree order only)
 
     bfsmi::Ctrl* h_ctrl = nullptr;      // pinned host mirror
-    bfsmi::MsCtrl* h_ms_ctrl = nullptr; // pinned host mirror
+    bfsmi::Ctrl* h_ms_ctrl = nullptr;   // pinned host mirror
+    hipStream_t cap_stream = nullptr;   // private stream for graph capture
+    hipGraphExec_t ms_graph = nullptr;  // captured batch levels
+    int ms_graph_ept = 0;
+    int32_t* h_roots = nullptr;         // pinned staging for batch roots
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing
 
     // options
-    int ept = 4;
+    int ept = 8;
     int frontier_mode = 0;  // 0 auto, 1 list only, 2 bitmap whenever possible
     int loop_driver = 0;    // 0 auto, 1 host, 2 device loop for small frontiers
-    int batch_tile = 1024;
+    int batch_tile = 1024;  // edges per workgroup in the batch expansion
     int grid_wgs = 8;
+    int profile = 0;
+    int use_summary = 1;
 
     std::atomic<int> busy{0};
 };

@@ -1,0 +1,512 @@
+// C ABI: serving (bfs_server_*, bfs_submit, bfs_poll).
+//
+// A worker thread owns every device launch.  Each registered graph has its
+// own stream; while a graph has queries, it runs a multi-source batch (the
+// kernels of msbfs.hip) whose 64 lanes are filled from the graph's queue at
+// level boundaries: a query joins a free lane with its root at depth 0 and
+// lane_start = level - 1, the batch keeps expanding the union frontier of
+// all live lanes, and a lane retires at the first level that finds nothing
+// for it; its seen bits are then cleared before the lane is reused.  The
+// batch state and each query's int16 result live in the caller's device
+// arena; a graph's batch starts only when its state fits the free arena
+// (admission by HBM budget), and a query joins only when its result fits.
+// Different graphs' batches run concurrently on their streams.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "runtime.h"
+
+namespace bfsmi {
+
+static int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// First-fit allocator over the caller's arena (offsets, 256-byte aligned).
+class Arena {
+public:
+    void init(char* base, size_t size)
+    {
+        base_ = base;
+        size_ = size / 256 * 256;
+        free_.clear();
+        if (size_) free_[0] = size_;
+    }
+    char* alloc(size_t bytes)
+    {
+        bytes = align256(bytes ? bytes : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                used_[off] = bytes;
+                return base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(char* p)
+    {
+        if (!p) return;
+        const size_t off = (size_t)(p - base_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t len = u->second;
+        used_.erase(u);
+        size_t start = off;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && nx->first == off + len) {
+            len += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(off);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                start = pv->first;
+                len += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = len;
+    }
+    size_t size() const { return size_; }
+
+private:
+    char* base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;
+    std::unordered_map<size_t, size_t> used_;
+};
+
+struct SrvQuery {
+    int32_t graph = 0;
+    int32_t root = 0;
+    int64_t submit_ns = 0, admit_ns = 0, done_ns = 0;
+    int32_t lanes = 0;
+    int16_t* result = nullptr;  // arena, int16[V]
+    int state = 0;              // 0 pending, 1 running, 2 done, 3 failed
+    int err = 0;
+};
+
+// Device state of one running batch, carved from one arena block.
+struct SrvBatch {
+    char* mem = nullptr;
+    uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
+    int32_t* q[2] = {nullptr, nullptr};
+    int32_t* deg = nullptr;
+    int64_t* cumul = nullptr;
+    int64_t* bsum = nullptr;
+    int32_t* tile_k = nullptr;
+    Ctrl* ctrl = nullptr;
+    int16_t** lane_out = nullptr;  // device table of 64 result pointers
+    int32_t* lane_start = nullptr; // device int32[64]
+    int32_t* join = nullptr;       // device int32[128] (root, lane) pairs
+    uint64_t lane_ticket[64] = {};
+    int64_t lane_age[64] = {};     // levels run since the lane joined
+    uint64_t active = 0;
+    int parity = 0;
+    bool in_flight = false;
+};
+
+struct SrvGraph {
+    bfs_graph* g = nullptr;
+    size_t state_bytes = 0;
+    std::deque<uint64_t> pending;
+    SrvBatch* batch = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    Ctrl* h_ctrl = nullptr;        // pinned
+    int16_t** h_lane_out = nullptr;  // pinned staging for the lane table
+    int32_t* h_join = nullptr;     // pinned staging for joins
+};
+
+static size_t batch_state_bytes(const bfs_graph* g)
+{
+    const size_t V = (size_t)g->V;
+    const size_t nblk = (V + kScanChunk - 1) / kScanChunk;
+    const size_t ntile = (size_t)((g->nnz + kMinTile - 1) / kMinTile);
+    size_t b = 0;
+    b += 3 * align256(V * 8);
+    b += 3 * align256(V * 4);
+    b += align256((V + 1) * 8);
+    b += align256((nblk + 1) * 8);
+    b += align256((ntile + 2) * 4);
+    b += align256(sizeof(Ctrl)) + align256(64 * 8) + align256(64 * 4) + align256(128 * 4);
+    return b;
+}
+
+}  // namespace bfsmi
+
+using namespace bfsmi;
+
+struct bfs_server {
+    Arena arena;
+    int device = 0;
+    bfs_server_config cfg{64, 8, 0};
+    std::mutex mu;
+    std::condition_variable cv;       // wakes the worker
+    std::condition_variable idle_cv;  // signals drain()
+    std::vector<SrvGraph> graphs;
+    std::unordered_map<uint64_t, SrvQuery> queries;
+    uint64_t next_ticket = 1;
+    int64_t outstanding = 0;
+    std::atomic<bool> stop{false};
+    int worker_err = 0;
+    std::thread worker;
+    void run();
+    bool step_graph(SrvGraph& G, int gid);
+};
+
+namespace {
+
+hipError_t enqueue_srv_level(const bfs_graph* g, SrvBatch* B, hipStream_t s, int parity)
+{
+    const int ept = std::max(1, g->batch_tile / kWG);
+    const int64_t tile_cap = (g->nnz + kMinTile - 1) / kMinTile + 1;
+    const int scan = g->num_cus * 2;
+    const int expand = g->num_cus * std::min(8, ms_expand_blocks_per_cu(ept));
+    const int fin = g->num_cus * 4;
+    return launch_ms_level(s, scan, expand, fin, ept, g->V, tile_cap, g->s_off, g->s_col, g->orig,
+                           B->q[parity], B->q[parity ^ 1], B->deg, B->bsum, B->cumul, B->tile_k,
+                           B->seen, B->front, B->next, B->lane_out, B->lane_start, B->ctrl);
+}
+
+}  // namespace
+
+// One scheduling step for graph G; returns true when it launched work.
+// Called by the worker with mu held; device calls are short and async.
+bool bfs_server::step_graph(SrvGraph& G, int gid)
+{
+    const bfs_graph* g = G.g;
+    SrvBatch* B = G.batch;
+    if (!B) {
+        if (G.pending.empty()) return false;
+        int running = 0;
+        for (const auto& o : graphs) running += o.batch != nullptr;
+        if (running >= cfg.max_inflight) return false;
+        char* mem = arena.alloc(G.state_bytes);
+        if (!mem) return false;  // over budget: wait for memory to free up
+        B = new SrvBatch();
+        B->mem = mem;
+        char* p = mem;
+        auto take = [&](size_t bytes) {
+            char* at = p;
+            p += align256(bytes);
+            return at;
+        };
+        const size_t V = (size_t)g->V;
+        B->seen = (uint64_t*)take(V * 8);
+        B->front = (uint64_t*)take(V * 8);
+        B->next = (uint64_t*)take(V * 8);
+        B->q[0] = (int32_t*)take(V * 4);
+        B->q[1] = (int32_t*)take(V * 4);
+        B->deg = (int32_t*)take(V * 4);
+        B->cumul = (int64_t*)take((V + 1) * 8);
+        B->bsum = (int64_t*)take(((V + kScanChunk - 1) / kScanChunk + 1) * 8);
+        B->tile_k = (int32_t*)take((size_t)((g->nnz + kMinTile - 1) / kMinTile + 2) * 4);
+        B->ctrl = (Ctrl*)take(sizeof(Ctrl));
+        B->lane_out = (int16_t**)take(64 * 8);
+        B->lane_start = (int32_t*)take(64 * 4);
+        B->join = (int32_t*)take(128 * 4);
+        G.batch = B;
+        if (launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->ctrl) !=
+            hipSuccess)
+            worker_err = BFS_ERR_HIP;
+    }
+    if (B->in_flight) {
+        if (hipEventQuery(G.ev) != hipSuccess) return false;
+        B->in_flight = false;
+        const Ctrl& c = *G.h_ctrl;
+        const int64_t t = now_ns();
+        uint64_t retired = B->active & ~c.last_alive;
+        if (c.err || c.overflow) retired = B->active;  // fail every running lane
+        for (int b = 0; b < 64; ++b) {
+            if (!((retired >> b) & 1ull)) continue;
+            auto it = queries.find(B->lane_ticket[b]);
+            if (it != queries.end()) {
+                it->second.done_ns = t;
+                it->second.state = (c.err || c.overflow) ? 3 : 2;
+                it->second.err = c.err ? BFS_ERR_HIP : (c.overflow ? BFS_ERR_DEPTH : 0);
+            }
+            --outstanding;
+        }
+        B->active &= ~retired;
+        if (retired) {
+            if (c.err || c.overflow) {
+                (void)launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->ctrl);
+            } else {
+                (void)launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->seen, retired);
+            }
+            idle_cv.notify_all();
+        }
+    }
+    // boundary: fill free lanes from the queue (FIFO, while results fit)
+    int n_join = 0;
+    const uint64_t lane_cap = cfg.max_lanes >= 64 ? ~0ull : ((1ull << cfg.max_lanes) - 1);
+    while (!G.pending.empty() && (~B->active & lane_cap)) {
+        const uint64_t ticket = G.pending.front();
+        SrvQuery& q = queries[ticket];
+        char* res = arena.alloc((size_t)g->V * 2);
+        if (!res) break;
+        G.pending.pop_front();
+        const int b = __builtin_ctzll(~B->active & lane_cap);
+        B->active |= 1ull << b;
+        B->lane_ticket[b] = ticket;
+        B->lane_age[b] = 0;
+        q.result = reinterpret_cast<int16_t*>(res);
+        q.state = 1;
+        q.admit_ns = now_ns();
+        G.h_join[2 * n_join] = q.root;
+        G.h_join[2 * n_join + 1] = b;
+        G.h_lane_out[b] = q.result;
+        (void)launch_fill16(G.stream, g->num_cus * 2, q.result, g->V, (int16_t)-1);
+        ++n_join;
+    }
+    if (n_join) {
+        const int lanes = __builtin_popcountll(B->active);
+        for (int i = 0; i < n_join; ++i) queries[B->lane_ticket[G.h_join[2 * i + 1]]].lanes = lanes;
+        if (hipMemcpyAsync(B->lane_out, G.h_lane_out, 64 * sizeof(int16_t*), hipMemcpyHostToDevice,
+                           G.stream) != hipSuccess ||
+            hipMemcpyAsync(B->join, G.h_join, (size_t)n_join * 2 * sizeof(int32_t),
+                           hipMemcpyHostToDevice, G.stream) != hipSuccess ||
+            launch_srv_join(G.stream, g->V, n_join, B->join, g->rank, B->seen, B->front,
+                            B->lane_out, B->lane_start, B->q[B->parity], B->ctrl) != hipSuccess)
+            worker_err = BFS_ERR_HIP;
+    }
+    if (!B->active) {
+        // nothing running and nothing admitted: release the batch
+        if (hipStreamSynchronize(G.stream) != hipSuccess) worker_err = BFS_ERR_HIP;
+        arena.release(B->mem);
+        delete B;
+        G.batch = nullptr;
+        return false;
+    }
+    // levels per round: 1 while every lane is young, more for deep searches
+    int64_t oldest = 0;
+    for (int b = 0; b < 64; ++b)
+        if ((B->active >> b) & 1ull) oldest = std::max(oldest, B->lane_age[b]);
+    const int K = oldest < 32 ? 1 : (oldest < 256 ? 4 : 16);
+    for (int k = 0; k < K; ++k) {
+        if (enqueue_srv_level(g, B, G.stream, B->parity) != hipSuccess) worker_err = BFS_ERR_HIP;
+        B->parity ^= 1;
+    }
+    for (int b = 0; b < 64; ++b)
+        if ((B->active >> b) & 1ull) B->lane_age[b] += K;
+    if (hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, G.stream) !=
+            hipSuccess ||
+        hipEventRecord(G.ev, G.stream) != hipSuccess)
+        worker_err = BFS_ERR_HIP;
+    B->in_flight = true;
+    (void)gid;
+    return true;
+}
+
+void bfs_server::run()
+{
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop.load()) {
+        bool busy = false;
+        bool waiting = false;
+        for (size_t i = 0; i < graphs.size(); ++i) {
+            busy |= step_graph(graphs[i], (int)i);
+            waiting |= graphs[i].batch != nullptr || !graphs[i].pending.empty();
+        }
+        if (!busy) {
+            // poll in-flight rounds at a fine grain; sleep when idle
+            if (waiting) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                cv.wait_for(lk, std::chrono::milliseconds(5));
+            }
+        }
+    }
+}
+
+extern "C" {
+
+int bfs_server_create(bfs_server** out, void* d_arena, size_t arena_bytes,
+                      const bfs_server_config* cfg)
+{
+    if (!out) return fail(BFS_ERR_INVALID, "server out-pointer is NULL");
+    *out = nullptr;
+    if (!d_arena || arena_bytes < 256) return fail(BFS_ERR_INVALID, "arena is NULL or too small");
+    if ((uintptr_t)d_arena % 256) return fail(BFS_ERR_INVALID, "arena not 256-byte aligned");
+    bfs_server_config c{64, 8, 0};
+    if (cfg) {
+        c = *cfg;
+        if (c.max_lanes < 1 || c.max_lanes > 64) return fail(BFS_ERR_INVALID, "max_lanes must be 1..64");
+        if (c.max_inflight < 1) return fail(BFS_ERR_INVALID, "max_inflight must be >= 1");
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BFS_ERR_NO_DEVICE, "no HIP device");
+    bfs_server* s = new (std::nothrow) bfs_server();
+    if (!s) return fail(BFS_ERR_INVALID, "out of host memory");
+    s->cfg = c;
+    s->arena.init(static_cast<char*>(d_arena), arena_bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, d_arena) == hipSuccess && attr.type == hipMemoryTypeDevice)
+        dev = attr.device;
+    (void)hipGetLastError();
+    s->device = dev;
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return ok();
+}
+
+int bfs_server_add_graph(bfs_server* s, bfs_graph* g, int32_t* graph_id)
+{
+    if (!s || !g || !graph_id) return fail(BFS_ERR_INVALID, "NULL argument");
+    SrvGraph G;
+    G.g = g;
+    G.state_bytes = batch_state_bytes(g);
+    if (G.state_bytes + align256((size_t)g->V * 2) > s->arena.size())
+        return fail(BFS_ERR_BUDGET, "graph needs %zu arena bytes, arena has %zu",
+                    G.state_bytes + align256((size_t)g->V * 2), s->arena.size());
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    hipError_t e = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&G.ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&G.h_ctrl, sizeof(Ctrl) + 64 * sizeof(int16_t*) + 128 * sizeof(int32_t),
+                          hipHostMallocDefault);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (G.stream) (void)hipStreamDestroy(G.stream);
+        if (G.ev) (void)hipEventDestroy(G.ev);
+        return hip_fail(e, "server graph resources");
+    }
+    G.h_lane_out = reinterpret_cast<int16_t**>(G.h_ctrl + 1);
+    G.h_join = reinterpret_cast<int32_t*>(G.h_lane_out + 64);
+    std::memset(G.h_lane_out, 0, 64 * sizeof(int16_t*));
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->graphs.push_back(G);
+    *graph_id = (int32_t)s->graphs.size() - 1;
+    return ok();
+}
+
+int bfs_submit(bfs_server* s, int32_t graph_id, int32_t root, uint64_t* ticket)
+{
+    if (!s || !ticket) return fail(BFS_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop.load()) return fail(BFS_ERR_INVALID, "server is stopping");
+    if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size())
+        return fail(BFS_ERR_INVALID, "unknown graph id %d", graph_id);
+    SrvGraph& G = s->graphs[graph_id];
+    if (root < 0 || root >= G.g->V) return fail(BFS_ERR_INVALID, "root %d outside [0, %d)", root, G.g->V);
+    const uint64_t t = s->next_ticket++;
+    SrvQuery q;
+    q.graph = graph_id;
+    q.root = root;
+    q.submit_ns = now_ns();
+    s->queries.emplace(t, q);
+    G.pending.push_back(t);
+    ++s->outstanding;
+    *ticket = t;
+    s->cv.notify_one();
+    return ok();
+}
+
+int bfs_poll(bfs_server* s, uint64_t ticket, int32_t* dst_levels, bfs_timing* tm)
+{
+    if (!s) return fail(BFS_ERR_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->queries.find(ticket);
+    if (it == s->queries.end()) return fail(BFS_ERR_TICKET, "unknown ticket %llu", (unsigned long long)ticket);
+    SrvQuery q = it->second;
+    if (q.state < 2) return BFS_PENDING;
+    const int32_t V = s->graphs[q.graph].g->V;
+    int rc = BFS_OK;
+    if (q.state == 3) {
+        rc = fail(q.err ? q.err : BFS_ERR_HIP, "query failed on the device");
+    } else if (dst_levels) {
+        lk.unlock();
+        std::vector<int16_t> tmp((size_t)V);
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(s->device);
+        hipError_t e = hipMemcpy(tmp.data(), q.result, (size_t)V * 2, hipMemcpyDeviceToHost);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) return hip_fail(e, "result copy");
+        int32_t lv = -1;
+        for (int32_t v = 0; v < V; ++v) {
+            dst_levels[v] = tmp[(size_t)v];
+            lv = std::max<int32_t>(lv, tmp[(size_t)v]);
+        }
+        q.lanes = q.lanes ? q.lanes : 1;
+        lk.lock();
+        it = s->queries.find(ticket);
+        if (tm) tm->levels = lv + 1;
+    }
+    if (tm) {
+        tm->submit_ns = q.submit_ns;
+        tm->admit_ns = q.admit_ns;
+        tm->done_ns = q.done_ns;
+        tm->lanes_in_batch = q.lanes;
+        if (!dst_levels || q.state == 3) tm->levels = 0;
+    }
+    if (it != s->queries.end()) {
+        s->arena.release(reinterpret_cast<char*>(it->second.result));
+        s->queries.erase(it);
+    }
+    s->cv.notify_one();
+    return rc == BFS_OK ? ok() : rc;
+}
+
+int bfs_server_drain(bfs_server* s)
+{
+    if (!s) return fail(BFS_ERR_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->idle_cv.wait(lk, [s] { return s->outstanding <= 0 || s->worker_err != 0; });
+    if (s->worker_err) return fail(s->worker_err, "server worker failed");
+    return ok();
+}
+
+int bfs_server_destroy(bfs_server* s)
+{
+    if (!s) return ok();
+    s->stop.store(true);
+    s->cv.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    for (auto& G : s->graphs) {
+        if (G.stream) (void)hipStreamSynchronize(G.stream);
+        if (G.batch) {
+            s->arena.release(G.batch->mem);
+            delete G.batch;
+        }
+        if (G.stream) (void)hipStreamDestroy(G.stream);
+        if (G.ev) (void)hipEventDestroy(G.ev);
+        if (G.h_ctrl) (void)hipHostFree(G.h_ctrl);
+    }
+    (void)hipSetDevice(prev);
+    delete s;
+    return ok();
+}
+
+}  // extern "C"

@@ -54,24 +54,33 @@ def check(p, g, G, root, mode=0, ept=4, want_parents=True, directed=False):
 
 def test_duplicates_and_self_loops(bfsmi):
     g = graphgen.from_edges(6, [0, 0, 0, 1, 1, 2, 3, 4], [1, 1, 0, 1, 2, 3, 4, 5])
-    G = bfsmi.Graph.from_csr(g.off, g.col)
-    for r in range(6):
-        check(bfsmi, g, G, r)
+    for flags in _flag_variants(bfsmi):
+        G = bfsmi.Graph.from_csr(g.off, g.col, flags=flags)
+        for r in range(6):
+            check(bfsmi, g, G, r)
 
 
 def test_path_and_disconnected(bfsmi):
     n = 2000
     src = np.concatenate([np.arange(999), np.arange(1000, 1999)])
     g = graphgen.from_edges(n, src, src + 1)
-    G = bfsmi.Graph.from_csr(g.off, g.col)
-    for root in (0, 500, 1500, 1999):
-        check(bfsmi, g, G, root)
+    for flags in _flag_variants(bfsmi):
+        G = bfsmi.Graph.from_csr(g.off, g.col, flags=flags)
+        for root in (0, 500, 1500, 1999):
+            check(bfsmi, g, G, root)
 
 
-@pytest.fixture(scope="module")
-def rmat16(bfsmi):
+@pytest.fixture(scope="module", params=["plain", "degree_order"])
+def rmat16(bfsmi, request):
     g = graphgen.rmat(16)
-    return g, bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_VALIDATE_CSR)
+    flags = bfsmi.BFS_VALIDATE_CSR
+    if request.param == "degree_order":
+        flags |= bfsmi.BFS_DEGREE_ORDER
+    return g, bfsmi.Graph.from_csr(g.off, g.col, flags=flags)
+
+
+def _flag_variants(p):
+    return [0, p.BFS_DEGREE_ORDER]
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
@@ -115,9 +124,10 @@ def test_repeatable(bfsmi, rmat16):
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (1, 300), (37, 23), (128, 128)])
-def test_grids_manhattan(bfsmi, w, h):
+@pytest.mark.parametrize("dord", [0, 1])
+def test_grids_manhattan(bfsmi, w, h, dord):
     g = graphgen.grid(w, h)
-    G = bfsmi.Graph.from_csr(g.off, g.col)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER if dord else 0)
     r_, c_ = np.divmod(np.arange(g.V), w)
     for root in sorted({0, g.V - 1, (h // 2) * w + w // 2}):
         check(bfsmi, g, G, root)
@@ -130,10 +140,11 @@ def test_hub_star(bfsmi):
     # one vertex of degree 200k: a single frontier entry spans many tiles
     n = 200_001
     g = graphgen.from_edges(n, np.zeros(n - 1, np.int64), np.arange(1, n))
-    G = bfsmi.Graph.from_csr(g.off, g.col)
-    for ept in (1, 8):
-        check(bfsmi, g, G, 0, ept=ept)
-        check(bfsmi, g, G, 77, ept=ept)
+    for flags in _flag_variants(bfsmi):
+        G = bfsmi.Graph.from_csr(g.off, g.col, flags=flags)
+        for ept in (1, 8):
+            check(bfsmi, g, G, 0, ept=ept)
+            check(bfsmi, g, G, 77, ept=ept)
 
 
 def test_directed_zero_outdegree(bfsmi):
@@ -148,10 +159,11 @@ def test_directed_zero_outdegree(bfsmi):
     src.append(movers)
     dst.append(rng.integers(1, n, size=500))
     g = graphgen.from_edges(n, np.concatenate(src), np.concatenate(dst), symmetric=False)
-    G = bfsmi.Graph.from_csr(g.off, g.col)
-    for mode in (0, 1, 2):
-        check(bfsmi, g, G, 0, mode=mode, directed=True)
-        check(bfsmi, g, G, int(movers[0]), mode=mode, directed=True)
+    for flags in _flag_variants(bfsmi):
+        G = bfsmi.Graph.from_csr(g.off, g.col, flags=flags)
+        for mode in (0, 1, 2):
+            check(bfsmi, g, G, 0, mode=mode, directed=True)
+            check(bfsmi, g, G, int(movers[0]), mode=mode, directed=True)
 
 
 def test_bad_arguments_on_gpu(bfsmi, rmat16):
@@ -182,9 +194,33 @@ def test_bad_arguments_on_gpu(bfsmi, rmat16):
     assert e.value.code == bfsmi.BFS_ERR_INVALID
 
 
+@pytest.mark.parametrize("summary", [0, 1, 2])
+@pytest.mark.parametrize("dord", [0, 1])
+def test_visited_summary(bfsmi, summary, dord):
+    g = graphgen.rmat(15)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER if dord else 0)
+    G.set_option(bfsmi.BFS_OPT_VISITED_SUMMARY, summary)
+    for r in graphgen.pick_roots(g, 3, 21):
+        for mode in (0, 1, 2):
+            check(bfsmi, g, G, int(r), mode=mode)
+
+
+def test_visited_summary_odd_sizes(bfsmi):
+    # V not a multiple of 32 or of the summary block: tail bits must not
+    # count as open vertices, and a fully visited graph must still end
+    for n in (33, 1000, 1025, 4097):
+        src = np.arange(n - 1)
+        g = graphgen.from_edges(n, np.zeros(n - 1, np.int64), src + 1)   # star
+        G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+        for r in (0, n - 1):
+            for mode in (0, 2):
+                check(bfsmi, g, G, r, mode=mode)
+
+
 @pytest.mark.skipif(os.environ.get("BFSMI_BIG", "1") == "0", reason="large graphs disabled")
-def test_rmat20_parity(bfsmi):
+@pytest.mark.parametrize("dord", [0, 1])
+def test_rmat20_parity(bfsmi, dord):
     g = graphgen.rmat(20)
-    G = bfsmi.Graph.from_csr(g.off, g.col)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER if dord else 0)
     for r in graphgen.pick_roots(g, 3, graphgen.root_seed(20)):
         check(bfsmi, g, G, int(r))

@@ -1,0 +1,168 @@
+"""Serving (bfs_server_*): every ticket's levels must equal the single-root
+oracle for that query alone (tolerance 0), whatever else was in flight.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bfsmi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1408_1605_amd as p
+    p.load()
+    return p
+
+
+def wait_all(p, s, tickets, V_of, timeout=60.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            buf = np.empty(V_of[t], dtype=np.int32)
+            code, tm = p.bfs_poll(s, t, buf)
+            if code == p.BFS_OK:
+                out[t] = (buf, tm)
+        assert time.time() - t0 < timeout, "queries did not finish"
+        time.sleep(0.001)
+    return out
+
+
+@pytest.fixture(scope="module")
+def pool(bfsmi):
+    graphs = [graphgen.rmat(12), graphgen.rmat(14, seed=77), graphgen.grid(40, 30),
+              graphgen.rmat(13, seed=5)]
+    handles = [bfsmi.Graph.from_csr(graphs[0].off, graphs[0].col),
+               bfsmi.Graph.from_csr(graphs[1].off, graphs[1].col, flags=bfsmi.BFS_DEGREE_ORDER),
+               bfsmi.Graph.from_csr(graphs[2].off, graphs[2].col),
+               bfsmi.Graph.from_csr(graphs[3].off, graphs[3].col)]
+    return graphs, handles
+
+
+def make_server(p, handles, arena_mb=512, lanes=64, inflight=8, arena_bytes=None):
+    nbytes = arena_bytes if arena_bytes is not None else arena_mb << 20
+    arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = p.bfs_server_create(arena, max_lanes=lanes, max_inflight=inflight)
+    ids = [p.bfs_server_add_graph(s, h.handle) for h in handles]
+    return s, ids, arena
+
+
+def test_serve_mix_matches_oracle(bfsmi, pool):
+    graphs, handles = pool
+    s, ids, arena = make_server(bfsmi, handles)
+    rng = np.random.default_rng(1)
+    tickets, meta = [], {}
+    for i in range(300):
+        gi = int(rng.integers(0, len(graphs)))
+        g = graphs[gi]
+        r = int(rng.integers(0, g.V))
+        t = bfsmi.bfs_submit(s, ids[gi], r)
+        tickets.append(t)
+        meta[t] = (gi, r)
+        if i % 50 == 0:
+            time.sleep(0.002)  # let some run before others arrive
+    _say("submitted", len(tickets))
+    res = wait_all(bfsmi, s, tickets, {t: graphs[meta[t][0]].V for t in tickets})
+    for t in tickets:
+        gi, r = meta[t]
+        exp = oracle.bfs(graphs[gi].off, graphs[gi].col, r).level
+        got, tm = res[t]
+        assert np.array_equal(got, exp), (gi, r)
+        assert tm.levels == int(exp.max()) + 1
+        assert tm.done_ns >= tm.admit_ns >= tm.submit_ns > 0
+    bfsmi.bfs_server_drain(s)
+    bfsmi.bfs_server_destroy(s)
+    del arena
+
+
+def test_serve_alone_equals_mix(bfsmi, pool):
+    graphs, handles = pool
+    g, h = graphs[1], handles[1]
+    root = int(graphgen.pick_roots(g, 1, 3)[0])
+    s, ids, arena = make_server(bfsmi, [h])
+    t_alone = bfsmi.bfs_submit(s, ids[0], root)
+    alone = wait_all(bfsmi, s, [t_alone], {t_alone: g.V})[t_alone][0]
+    others = [bfsmi.bfs_submit(s, ids[0], int(x)) for x in graphgen.pick_roots(g, 63, 11)]
+    t_mix = bfsmi.bfs_submit(s, ids[0], root)
+    res = wait_all(bfsmi, s, others + [t_mix], {t: g.V for t in others + [t_mix]})
+    assert np.array_equal(res[t_mix][0], alone)
+    bfsmi.bfs_server_destroy(s)
+    del arena
+
+
+def test_serve_budget_queues(bfsmi, pool):
+    graphs, handles = pool
+    g, h = graphs[0], handles[0]
+    # room for one batch state and three result buffers at a time, so most
+    # queries wait in the queue for memory
+    def al(x):
+        return (x + 255) // 256 * 256
+    V = g.V
+    state = (3 * al(8 * V) + 3 * al(4 * V) + al(8 * (V + 1)) + al(8 * ((V + 2047) // 2048 + 1))
+             + al(4 * ((g.nnz + 255) // 256 + 2)) + al(128) + al(512) + al(256) + al(512))
+    s, ids, arena = make_server(bfsmi, [h], arena_bytes=state + 3 * al(2 * V) + 256)
+    roots = graphgen.pick_roots(g, 40, 5)
+    ts = [bfsmi.bfs_submit(s, ids[0], int(r)) for r in roots]
+    res = wait_all(bfsmi, s, ts, {t: g.V for t in ts})
+    for t, r in zip(ts, roots):
+        assert np.array_equal(res[t][0], oracle.bfs(g.off, g.col, int(r)).level)
+    bfsmi.bfs_server_destroy(s)
+    del arena
+
+
+def test_serve_never_fits(bfsmi, pool):
+    graphs, handles = pool
+    arena = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = bfsmi.bfs_server_create(arena)
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.bfs_server_add_graph(s, handles[1].handle)
+    assert e.value.code == bfsmi.BFS_ERR_BUDGET
+    bfsmi.bfs_server_destroy(s)
+
+
+def test_serve_bad_tickets_and_roots(bfsmi, pool):
+    graphs, handles = pool
+    s, ids, arena = make_server(bfsmi, handles[:1], arena_mb=64)
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.bfs_poll(s, 12345)
+    assert e.value.code == bfsmi.BFS_ERR_TICKET
+    with pytest.raises(bfsmi.BFSError):
+        bfsmi.bfs_submit(s, ids[0], graphs[0].V)
+    with pytest.raises(bfsmi.BFSError):
+        bfsmi.bfs_submit(s, 99, 0)
+    t = bfsmi.bfs_submit(s, ids[0], 0)
+    wait_all(bfsmi, s, [t], {t: graphs[0].V})
+    with pytest.raises(bfsmi.BFSError) as e:  # retired
+        bfsmi.bfs_poll(s, t)
+    assert e.value.code == bfsmi.BFS_ERR_TICKET
+    bfsmi.bfs_server_destroy(s)
+
+
+def test_serve_deep_grid(bfsmi):
+    # a 300-long path needs more levels than a lane round of 1 or 4
+    g = graphgen.grid(300, 2)
+    h = bfsmi.Graph.from_csr(g.off, g.col)
+    s, ids, arena = make_server(bfsmi, [h], arena_mb=64)
+    ts = [bfsmi.bfs_submit(s, ids[0], r) for r in (0, 299, 150, 599)]
+    res = wait_all(bfsmi, s, ts, {t: g.V for t in ts})
+    for t, r in zip(ts, (0, 299, 150, 599)):
+        assert np.array_equal(res[t][0], oracle.bfs(g.off, g.col, r).level)
+    bfsmi.bfs_server_destroy(s)
