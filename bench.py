@@ -14,8 +14,11 @@ The JSON line also carries:
                   against the MI355X HBM peak of 8 TB/s;
   cpu_baseline -- the serial CPU oracle on one root of the same graph, on
                   this host's cores (one thread), in GTEPS;
-  batch, serve -- multi-source batch throughput and serving latency, when
-                  those paths are enabled (--batch / --serve).
+  batch        -- 64 roots in one multi-source batch on R-MAT scale 22:
+                  roots/s, and the speedup over 64 one-at-a-time searches;
+  serve        -- open-loop Poisson queries (2000/s) over 32 resident graphs
+                  (24 R-MAT scales 14-22, 8 grids 256k x 256k): p50/p99
+                  latency (completion - scheduled arrival) and completed QPS.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--scale S]
 """
@@ -67,6 +70,18 @@ def single_root(args, torch, np, graphgen, bfsmi):
     log("uploaded and created graph handle (flags %d) in %.1fs" % (flags, time.time() - t))
     if args.summary >= 0:
         G.set_option(bfsmi.BFS_OPT_VISITED_SUMMARY, args.summary)
+    tuned = None
+    if args.autotune:
+        from paper_1408_1605_amd import autotune
+        tuned = autotune.load_cached("rmat", args.scale)
+        if tuned is None:
+            best, table = autotune.tune_single(G, [int(r) for r in roots[:4]], log=log)
+            tuned = dict(best or {})
+            autotune.save("rmat", args.scale, {"single": tuned, "table": table})
+        else:
+            tuned = tuned.get("single", {})
+        autotune.apply(G, tuned)
+        log("autotuned configuration: %s" % tuned)
     if args.ept:
         G.set_option(bfsmi.BFS_OPT_EDGES_PER_THREAD, args.ept)
     G.set_option(bfsmi.BFS_OPT_PROFILE, 1)
@@ -142,6 +157,114 @@ def single_root(args, torch, np, graphgen, bfsmi):
     return res, g
 
 
+def batch_section(args, torch, np, graphgen, bfsmi):
+    """64 roots in one bfs_run_batch on R-MAT scale 22 vs 64 single-root
+    searches one at a time (parents skipped) on the same GPU and graph."""
+    scale = args.batch_scale
+    g = graphgen.rmat(scale)
+    roots = [int(r) for r in graphgen.pick_roots(g, 64, graphgen.root_seed(scale))]
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_WS_BATCH | bfsmi.BFS_DEGREE_ORDER)
+    out = torch.empty((64, g.V), dtype=torch.int8, device="cuda")
+    lv = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        bfsmi.bfs_run_batch(G.handle, roots, out)
+    torch.cuda.synchronize()
+    reps = args.batch_reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = bfsmi.bfs_run_batch(G.handle, roots, out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    bfsmi.bfs_run(G.handle, roots[0], lv, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in roots:
+        bfsmi.bfs_run(G.handle, r, lv, None)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    # rows vs the single-root path for a few roots (GPU against GPU; the
+    # oracle comparisons live in the tests)
+    ok = True
+    rows = out.cpu().numpy()
+    for i in (0, 31, 63):
+        bfsmi.bfs_run(G.handle, roots[i], lv, None)
+        torch.cuda.synchronize()
+        ok &= bool(np.array_equal(rows[i].astype(np.int32), lv.cpu().numpy()))
+    G.close()
+    res = {"graph": "rmat%d" % scale, "n_roots": 64, "batch_ms": round(t_batch * 1e3, 3),
+           "roots_per_s": round(64 / t_batch, 1), "sequential_roots_per_s": round(64 / t_seq, 1),
+           "speedup_vs_sequential": round(t_seq / t_batch, 2), "union_levels": st.levels,
+           "union_edges_scanned": st.edges_scanned, "rows_match_single_root": ok}
+    log("batch: %s" % res)
+    return res
+
+
+def serve_section(args, torch, np, graphgen, bfsmi):
+    """Open-loop Poisson queries over a pool of resident graphs."""
+    rng = np.random.default_rng(3000)
+    scales = rng.integers(14, 23, size=24)
+    graphs = [graphgen.rmat(int(sc), seed=3000 + i) for i, sc in enumerate(scales)]
+    graphs += [graphgen.grid(256 * k) for k in range(1, 9)]
+    handles = [bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER) for g in graphs]
+    nonzero = [np.nonzero(np.diff(g.off) > 0)[0] for g in graphs]
+    arena = torch.empty(args.serve_arena_gb << 30, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = bfsmi.bfs_server_create(arena, max_lanes=64, max_inflight=len(graphs))
+    ids = [bfsmi.bfs_server_add_graph(s, h.handle) for h in handles]
+    log("serve: %d graphs resident, %d GiB arena" % (len(graphs), args.serve_arena_gb))
+    rate, warm, dur = args.serve_rate, 1.0, args.serve_seconds
+    arr = np.random.default_rng(4000)
+    n = int(rate * (warm + dur) * 1.2) + 10
+    gaps = arr.exponential(1.0 / rate, size=n)
+    gsel = arr.integers(0, len(graphs), size=n)
+    rsel = arr.random(size=n)
+    bufs = {}
+    pending = {}
+    lat = []
+    done_in_window = 0
+    t_start = time.monotonic_ns()
+    sched = t_start
+    i = 0
+    end_ns = t_start + int((warm + dur) * 1e9)
+    while True:
+        now = time.monotonic_ns()
+        while i < n and sched <= now and sched < end_ns:
+            gi = int(gsel[i])
+            cand = nonzero[gi]
+            root = int(cand[int(rsel[i] * len(cand))])
+            t = bfsmi.bfs_submit(s, ids[gi], root)
+            pending[t] = (sched, gi)
+            sched += int(gaps[i] * 1e9)
+            i += 1
+        for t in list(pending):
+            gi = pending[t][1]
+            buf = bufs.get(gi)
+            if buf is None:
+                buf = bufs[gi] = np.empty(graphs[gi].V, dtype=np.int32)
+            code, tm = bfsmi.bfs_poll(s, t, buf)
+            if code == bfsmi.BFS_OK:
+                arrive, _ = pending.pop(t)
+                if arrive >= t_start + int(warm * 1e9):
+                    lat.append((tm.done_ns - arrive) / 1e6)
+                    if tm.done_ns <= end_ns:
+                        done_in_window += 1
+        if sched >= end_ns and not pending:
+            break
+        if time.monotonic_ns() > end_ns + int(30e9):
+            break
+    bfsmi.bfs_server_destroy(s)
+    for h in handles:
+        h.close()
+    lat = np.array(lat) if lat else np.zeros(1)
+    res = {"graphs": len(graphs), "offered_qps": rate, "measured_s": dur,
+           "completed": int(len(lat)), "qps": round(done_in_window / dur, 1),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "max_ms": round(float(lat.max()), 3), "unfinished": len(pending)}
+    log("serve: %s" % res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +276,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-degree-order", action="store_true")
     ap.add_argument("--summary", type=int, default=-1)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-scale", type=int, default=22)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-arena-gb", type=int, default=48)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -173,6 +304,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     res, g = single_root(args, torch, np, graphgen, bfsmi)
+    batch = None if args.no_batch else batch_section(args, torch, np, graphgen, bfsmi)
+    serve = None if args.no_serve else serve_section(args, torch, np, graphgen, bfsmi)
 
     out = {
         "metric": METRIC,
@@ -202,6 +335,10 @@ def main():
     if "cpu_baseline" in res:
         out["cpu_baseline"] = res["cpu_baseline"]
         out["parity_root0"] = res["parity_root0"]
+    if batch is not None:
+        out["batch"] = batch
+    if serve is not None:
+        out["serve"] = serve
     print(json.dumps(out), flush=True)
 
 

@@ -54,6 +54,8 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
     L.q0 = take((size_t)V * 4);
     L.q1 = take((size_t)V * 4);
     L.deg = take((size_t)V * 4);
+    L.rowstart = take((size_t)V * 8);
+    L.suid = take((size_t)V * 4);
     L.cumul = take(((size_t)V + 1) * 8);
     L.bsum = take((nblk + 1) * 8);
     L.tile_k = take((ntile_max + 2) * 4);
@@ -144,6 +146,8 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     g->q[0] = reinterpret_cast<int32_t*>(g->ws + L.q0);
     g->q[1] = reinterpret_cast<int32_t*>(g->ws + L.q1);
     g->deg = reinterpret_cast<int32_t*>(g->ws + L.deg);
+    g->rowstart = reinterpret_cast<int64_t*>(g->ws + L.rowstart);
+    g->suid = reinterpret_cast<int32_t*>(g->ws + L.suid);
     g->cumul = reinterpret_cast<int64_t*>(g->ws + L.cumul);
     g->bsum = reinterpret_cast<int64_t*>(g->ws + L.bsum);
     g->tile_k = reinterpret_cast<int32_t*>(g->ws + L.tile_k);
@@ -236,7 +240,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         const int64_t tile_cap = (nnz + kMinTile - 1) / kMinTile + 1;
         e = build_degree_order(s, V, nnz, d_row_offsets, d_col, g->rank, g->orig,
                                const_cast<int64_t*>(g->s_off), const_cast<int32_t*>(g->s_col),
-                               g->deg, g->bsum, g->tile_k, tile_cap,
+                               g->deg, g->rowstart, g->suid, g->bsum, g->tile_k, tile_cap,
                                reinterpret_cast<uint32_t*>(g->ws + L.hist), g->ctrl,
                                g->num_cus * 8);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -395,8 +399,9 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         const int32_t* Q = g->q[cur];
         int32_t* Qn = g->q[cur ^ 1];
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
-        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->deg, g->bsum, g->cumul, g->tile_k,
-                                tile_cap, tile, T, allow_bitmap, g->ctrl));
+        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
+                                g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
+                                g->ctrl));
         int64_t rmax = (int64_t)qlen * (int64_t)g->maxdeg;
         if (rmax > g->nnz) rmax = g->nnz;
         const int64_t tiles_ub = (rmax + tile - 1) / tile;
@@ -407,14 +412,13 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         const int grid = (int)std::max<int64_t>(
             1, std::min<int64_t>(tiles_ub, lds_sum ? xgrid_sum : xgrid_full));
         if (use_sum) {
-            const int64_t nthr = (int64_t)g->summary_blocks << (g->summary_shift - 7);
-            const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(grid_cap, (nthr + kWG - 1) / kWG));
+            const int gs = std::max(1, std::min(grid_cap, (g->summary_blocks + 31) / 32));
             BFS_HIP_TRY(launch_visited_summary(s, gs, g->V, g->W, g->vis, g->summary_shift,
                                                g->summary_blocks, g->summary, g->ctrl));
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
-        BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, Q, g->cumul, g->tile_k, g->s_off,
-                                  g->s_col, g->orig, g->summary, lds_sum ? sum_words : 0,
+        BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
+                                  g->tile_k, g->s_col, g->orig, g->summary, lds_sum ? sum_words : 0,
                                   g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, levels,
                                   parents, lvl, Qn, g->ctrl));
         xlaunches++;

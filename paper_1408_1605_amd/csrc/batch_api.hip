@@ -45,7 +45,8 @@ static BatchGrids batch_grids(bfs_graph* g)
 static hipError_t enqueue_level(bfs_graph* g, hipStream_t s, const BatchGrids& b, int parity)
 {
     return launch_ms_level(s, b.scan, b.expand, b.fin, b.ept, g->V, b.tile_cap, g->s_off, g->s_col,
-                           g->orig, g->q[parity], g->q[parity ^ 1], g->deg, g->bsum, g->cumul,
+                           g->orig, g->q[parity], g->q[parity ^ 1], g->deg, g->rowstart, g->suid,
+                           g->bsum, g->cumul,
                            g->tile_k, g->ms_seen, g->ms_front, g->ms_next, nullptr, nullptr,
                            g->ms_ctrl);
 }

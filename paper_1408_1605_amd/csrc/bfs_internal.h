@@ -43,20 +43,24 @@ hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root,
                        uint32_t* vis, uint32_t* vis_old, int32_t* Q, Ctrl* ctrl,
                        int grid_cap);
 
-hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen,
-                       const int64_t* off, int32_t* deg, int64_t* bsum,
-                       int64_t* cumul, int32_t* tile_k, int64_t tile_cap, int tile,
-                       int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl);
+// Degree scan of the frontier Q: deg, cumul (exclusive, cumul[qlen] = r),
+// rowstart[k] = off[Q[k]], uidv[k] = uid_map ? uid_map[Q[k]] : Q[k], and
+// tile_k (the entry holding each tile's first edge).
+hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int64_t* off,
+                       const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
+                       int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
+                       int tile, int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl);
 
 // Same scan with the frontier size taken from ctrl->qlen (fixed grid,
 // grid-stride); every kernel returns at once when ctrl->done is set.
 hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int64_t* off,
-                           int32_t* deg, int64_t* bsum, int64_t* cumul, int32_t* tile_k,
-                           int64_t tile_cap, int tile, Ctrl* ctrl);
+                           const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
+                           int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
+                           int tile, Ctrl* ctrl);
 
-hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int32_t* Q,
-                         const int64_t* cumul, const int32_t* tile_k,
-                         const int64_t* off, const int32_t* col, const int32_t* orig,
+hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int64_t* rowstart,
+                         const int32_t* uidv, const int64_t* cumul, const int32_t* tile_k,
+                         const int32_t* col, const int32_t* orig,
                          const uint32_t* summary, int32_t summary_words, int32_t shift,
                          int use_prefix, uint32_t* vis, uint32_t* vis_old, int32_t* level,
                          int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl);
@@ -88,7 +92,8 @@ hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* h_r
 hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid,
                            int ept, int32_t V, int64_t tile_cap, const int64_t* off,
                            const int32_t* col, const int32_t* orig, const int32_t* Q,
-                           int32_t* Qn, int32_t* deg, int64_t* bsum, int64_t* cumul,
+                           int32_t* Qn, int32_t* deg, int64_t* rowstart, int32_t* uidv,
+                           int64_t* bsum, int64_t* cumul,
                            int32_t* tile_k, uint64_t* seen, uint64_t* front, uint64_t* next,
                            int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl);
 int ms_expand_blocks_per_cu(int ept);
@@ -107,6 +112,7 @@ hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32
 hipError_t build_degree_order(hipStream_t s, int32_t V, int64_t nnz, const int64_t* off,
                               const int32_t* col, int32_t* rank, int32_t* orig,
                               int64_t* off_r, int32_t* col_r, int32_t* deg_tmp,
+                              int64_t* rowstart_tmp, int32_t* uid_tmp,
                               int64_t* bsum_tmp, int32_t* tile_k, int64_t tile_cap,
                               uint32_t* hist_tmp, Ctrl* ctrl, int grid_cap);
 

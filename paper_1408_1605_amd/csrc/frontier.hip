@@ -112,7 +112,10 @@ hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, const 
 
 __global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__ Q, int32_t qlen_arg,
                                                      const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ uid_map,
                                                      int32_t* __restrict__ deg,
+                                                     int64_t* __restrict__ rowstart,
+                                                     int32_t* __restrict__ uidv,
                                                      int64_t* __restrict__ bsum,
                                                      const Ctrl* __restrict__ ctrl, int dev)
 {
@@ -128,8 +131,11 @@ __global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__
             const int64_t k = base + j * kWG + threadIdx.x;
             if (k < qlen) {
                 const int32_t u = Q[k];
-                const int64_t d = off[u + 1] - off[u];
+                const int64_t a = off[u];
+                const int64_t d = off[u + 1] - a;
                 deg[k] = (int32_t)d;
+                rowstart[k] = a;
+                uidv[k] = uid_map ? uid_map[u] : u;
                 sum += d;
             }
         }
@@ -234,14 +240,14 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
 }
 
 hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int64_t* off,
-                       int32_t* deg, int64_t* bsum, int64_t* cumul, int32_t* tile_k,
-                       int64_t tile_cap, int tile, int64_t bitmap_threshold, int allow_bitmap,
-                       Ctrl* ctrl)
+                       const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
+                       int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
+                       int tile, int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl)
 {
     const int32_t nblk = (int32_t)(((int64_t)qlen + kScanChunk - 1) / kScanChunk);
     if (nblk > 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kWG), 0, s, Q, qlen, off, deg, bsum,
-                           ctrl, 0);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kWG), 0, s, Q, qlen, off, uid_map, deg,
+                           rowstart, uidv, bsum, ctrl, 0);
     }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, qlen, tile_cap, tile,
                        bitmap_threshold, allow_bitmap, cumul, tile_k, ctrl, 0);
@@ -253,11 +259,13 @@ hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int6
 }
 
 hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int64_t* off,
-                           int32_t* deg, int64_t* bsum, int64_t* cumul, int32_t* tile_k,
-                           int64_t tile_cap, int tile, Ctrl* ctrl)
+                           const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
+                           int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
+                           int tile, Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(kWG), 0, s, Q, 0, off, deg, bsum, ctrl, 1);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(kWG), 0, s, Q, 0, off, uid_map, deg,
+                       rowstart, uidv, bsum, ctrl, 1);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, 0, tile_cap, tile,
                        (int64_t)1 << 62, 0, cumul, tile_k, ctrl, 1);
     hipLaunchKernelGGL(k_scan_down, dim3(grid), dim3(kWG), 0, s, deg, 0, bsum, tile_cap, tile,
@@ -277,62 +285,94 @@ hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int6
 // frontier edges point to, fill the lowest ids, and at the heaviest level
 // most probes are answered by a register compare or an LDS bit.
 
+// One workgroup per summary word: 32 blocks of 2^shift ids.  Thread t of
+// the workgroup checks P = 2^(shift-8) consecutive bitmap words, so 8
+// consecutive threads cover one block; no atomics, one plain store per word.
 __global__ __launch_bounds__(kWG) void k_visited_summary(int32_t V, int32_t W,
                                                          const uint32_t* __restrict__ vis,
-                                                         int32_t shift, int32_t nblocks,
-                                                         uint32_t* __restrict__ summary,
-                                                         Ctrl* __restrict__ ctrl)
+                                                         int32_t shift, int32_t nwords,
+                                                         uint32_t* __restrict__ summary)
 {
-    // Thread t checks words 4t .. 4t+3 (ids 128t .. 128t+127).  A block of
-    // 2^shift ids (shift >= 10) spans G = 2^(shift-7) >= 8 threads; the
-    // summary starts all-ones and the first lane of each block's group clears
-    // the block's bit when the group saw an open (unvisited) id.
-    const int32_t G = 1 << (shift - 7);
-    const int g = G < 64 ? G : 64;
-    const int64_t nthreads = (int64_t)nblocks * G;
-    const int64_t stride = (int64_t)gridDim.x * kWG;
+    __shared__ uint32_t s_bits[kWG / 64];
+    const int32_t P = 1 << (shift - 8);
     const int lane = __lane_id();
-    for (int64_t t0 = (int64_t)blockIdx.x * kWG; t0 < nthreads; t0 += stride) {
-        const int64_t t = t0 + threadIdx.x;
-        uint32_t any_open = 0;
-        int32_t first_open = 0x7fffffff;
-        if (t < nthreads) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t w = t * 4 + j;
-                const uint32_t x = w < W ? vis[w] : 0u;
-                const int64_t lo = w * 32;
-                uint32_t valid = 0xffffffffu;  // ids at or beyond V count as visited
-                if (lo + 32 > V) valid = lo >= V ? 0u : ((1u << (V - lo)) - 1u);
-                const uint32_t open = ~x & valid;
-                if (open && !any_open) first_open = (int32_t)(lo + __builtin_ctz(open));
-                any_open |= open ? 1u : 0u;
-            }
+    const int wave = threadIdx.x >> 6;
+    for (int32_t sw = blockIdx.x; sw < nwords; sw += gridDim.x) {
+        const int64_t w0 = ((int64_t)sw * kWG + threadIdx.x) * P;
+        uint32_t open_any = 0;
+        for (int32_t j = 0; j < P; ++j) {
+            const int64_t w = w0 + j;
+            const uint32_t x = w < W ? vis[w] : 0u;
+            const int64_t lo = w * 32;
+            uint32_t valid = 0xffffffffu;  // ids at or beyond V count as visited
+            if (lo + 32 > V) valid = lo >= V ? 0u : ((1u << (V - lo)) - 1u);
+            open_any |= ~x & valid;
         }
-        uint32_t grp = any_open;
-        for (int d = 1; d < g; d <<= 1) grp |= __shfl_xor(grp, d, 64);
-        if (t < nthreads && (lane % g) == 0 && grp) {
-            const int64_t b = t / G;
-            atomicAnd(&summary[b >> 5], ~(1u << (b & 31)));
-        }
-        int32_t m = first_open;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t o = __shfl_xor(m, d, 64);
-            m = o < m ? o : m;
-        }
-        if (lane == 0 && m != 0x7fffffff) atomicMin(&ctrl->full_prefix, m);
+        uint32_t grp = open_any ? 1u : 0u;
+        grp |= __shfl_xor(grp, 1, 64);
+        grp |= __shfl_xor(grp, 2, 64);
+        grp |= __shfl_xor(grp, 4, 64);
+        const uint64_t full = __ballot(grp == 0);
+        // lanes 0, 8, .., 56 hold blocks 8*wave .. 8*wave+7 of this word
+        uint32_t bits = 0;
+        for (int i = 0; i < 8; ++i) bits |= (uint32_t)((full >> (8 * i)) & 1ull) << i;
+        if (lane == 0) s_bits[wave] = bits << (8 * wave);
+        __syncthreads();
+        if (threadIdx.x == 0) summary[sw] = s_bits[0] | s_bits[1] | s_bits[2] | s_bits[3];
+        __syncthreads();
     }
+}
+
+// full_prefix = first unvisited id: the first block whose summary bit is
+// clear, then the first open bit in that block's words.  One workgroup.
+__global__ __launch_bounds__(kWG) void k_visited_prefix(int32_t V, int32_t W,
+                                                        const uint32_t* __restrict__ vis,
+                                                        int32_t shift, int32_t nwords,
+                                                        const uint32_t* __restrict__ summary,
+                                                        Ctrl* __restrict__ ctrl)
+{
+    __shared__ int32_t s_min;
+    if (threadIdx.x == 0) s_min = 0x7fffffff;
+    __syncthreads();
+    int32_t first_word = 0x7fffffff;
+    for (int32_t i = threadIdx.x; i < nwords; i += kWG)
+        if (summary[i] != 0xffffffffu) { first_word = i; break; }
+    atomicMin(&s_min, first_word);
+    __syncthreads();
+    const int32_t sw = s_min;
+    __syncthreads();
+    if (sw == 0x7fffffff) {
+        if (threadIdx.x == 0) ctrl->full_prefix = V;  // everything visited
+        return;
+    }
+    const uint32_t bits = summary[sw];
+    const int32_t b = sw * 32 + __builtin_ctz(~bits);  // first non-full block
+    const int64_t wlo = ((int64_t)b << shift) >> 5;
+    const int64_t whi = (((int64_t)b + 1) << shift) >> 5;
+    if (threadIdx.x == 0) s_min = 0x7fffffff;
+    __syncthreads();
+    for (int64_t w = wlo + threadIdx.x; w < whi; w += kWG) {
+        const uint32_t x = w < W ? vis[w] : 0u;
+        const int64_t lo = w * 32;
+        uint32_t valid = 0xffffffffu;
+        if (lo + 32 > V) valid = lo >= V ? 0u : ((1u << (V - lo)) - 1u);
+        const uint32_t open = ~x & valid;
+        if (open) atomicMin(&s_min, (int32_t)(lo + __builtin_ctz(open)));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) ctrl->full_prefix = s_min == 0x7fffffff ? V : s_min;
 }
 
 hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
                                   const uint32_t* vis, int32_t shift, int32_t nblocks,
                                   uint32_t* summary, Ctrl* ctrl)
 {
+    const int32_t nwords = (nblocks + 31) / 32;
     if (grid < 1) grid = 1;
-    // bits start set ("full") and are cleared for blocks with an open id
-    hipError_t e = hipMemsetAsync(summary, 0xff, ((size_t)nblocks + 31) / 32 * 4, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_visited_summary, dim3(grid), dim3(kWG), 0, s, V, W, vis, shift, nblocks,
+    if (grid > nwords) grid = nwords;
+    hipLaunchKernelGGL(k_visited_summary, dim3(grid), dim3(kWG), 0, s, V, W, vis, shift, nwords,
+                       summary);
+    hipLaunchKernelGGL(k_visited_prefix, dim3(1), dim3(kWG), 0, s, V, W, vis, shift, nwords,
                        summary, ctrl);
     return hipGetLastError();
 }
@@ -347,10 +387,10 @@ hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
 // copied into LDS and answers the early test before any bitmap load.
 
 template <int EPT>
-__global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __restrict__ Q,
+__global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __restrict__ rowstart,
+                                                const int32_t* __restrict__ uidv,
                                                 const int64_t* __restrict__ cumul,
                                                 const int32_t* __restrict__ tile_k,
-                                                const int64_t* __restrict__ off,
                                                 const int32_t* __restrict__ col,
                                                 const int32_t* __restrict__ orig,
                                                 const uint32_t* __restrict__ summary,
@@ -372,6 +412,7 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
     const int32_t skip_below = use_prefix ? ctrl->full_prefix : 0;
     if ((int32_t)blockIdx.x >= ntiles) return;  // whole workgroup: uniform
 
+    StageRegs<EPT> cur = fetch_stage<EPT>(blockIdx.x, ntiles, cumul, rowstart, uidv, tile_k);
     for (int32_t w = threadIdx.x; w < summary_words; w += kWG) s_sum[w] = summary[w];
     __syncthreads();
 
@@ -379,7 +420,9 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
         int32_t uu[EPT], vv[EPT];
         bool ok[EPT];
         int64_t ee[EPT];
-        map_tile<EPT>(L, tile, r, Q, cumul, tile_k, off, col, orig, uu, vv, ok, ee);
+        map_tile<EPT>(L, cur, r, cumul, rowstart, uidv, col, uu, vv, ok, ee);
+        // the next tile's staging loads overlap this tile's probes
+        cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
 
         // Early visited test: summary (register / LDS), else a plain load of
         // the bitmap word (a stale word only lets more threads try the atomic).
@@ -443,8 +486,8 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int32_t* __rest
     }
 }
 
-hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int32_t* Q,
-                         const int64_t* cumul, const int32_t* tile_k, const int64_t* off,
+hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int64_t* rowstart,
+                         const int32_t* uidv, const int64_t* cumul, const int32_t* tile_k,
                          const int32_t* col, const int32_t* orig, const uint32_t* summary,
                          int32_t summary_words, int32_t shift, int use_prefix, uint32_t* vis,
                          uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
@@ -455,8 +498,9 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int3
     const size_t dyn = (size_t)summary_words * 4;
 #define BFS_EXPAND_CASE(E)                                                                        \
     case E:                                                                                      \
-        hipLaunchKernelGGL(k_expand<E>, dim3(grid), dim3(kWG), dyn, s, V, Q, cumul, tile_k, off,  \
-                           col, orig, summary, summary_words, shift, use_prefix, vis, vis_old,    \
+        hipLaunchKernelGGL(k_expand<E>, dim3(grid), dim3(kWG), dyn, s, V, rowstart, uidv, cumul,  \
+                           tile_k, col, orig, summary, summary_words, shift, use_prefix, vis,     \
+                           vis_old,                                                              \
                            level, parent,                                                        \
                            lvl, Qn, ctrl);                                                       \
         break;

@@ -113,10 +113,10 @@ hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* roo
 }
 
 template <int EPT>
-__global__ __launch_bounds__(kWG) void k_ms_expand(const int32_t* __restrict__ Q,
+__global__ __launch_bounds__(kWG) void k_ms_expand(const int64_t* __restrict__ rowstart,
+                                                   const int32_t* __restrict__ uidv,
                                                    const int64_t* __restrict__ cumul,
                                                    const int32_t* __restrict__ tile_k,
-                                                   const int64_t* __restrict__ off,
                                                    const int32_t* __restrict__ col,
                                                    const uint64_t* __restrict__ front,
                                                    const uint64_t* __restrict__ seen,
@@ -127,11 +127,13 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(const int32_t* __restrict__ Q
     if (ctrl->done) return;
     const int64_t r = ctrl->r;
     const int32_t ntiles = ctrl->ntiles;
+    StageRegs<EPT> cur = fetch_stage<EPT>(blockIdx.x, ntiles, cumul, rowstart, uidv, tile_k);
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         int32_t uu[EPT], vv[EPT];
         bool ok[EPT];
         int64_t ee[EPT];
-        map_tile<EPT>(L, tile, r, Q, cumul, tile_k, off, col, nullptr, uu, vv, ok, ee);
+        map_tile<EPT>(L, cur, r, cumul, rowstart, uidv, col, uu, vv, ok, ee);
+        cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
         uint64_t f[EPT], sn[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) f[j] = ok[j] ? front[uu[j]] : 0ull;
@@ -233,13 +235,13 @@ __global__ void k_ms_advance(Ctrl* __restrict__ ctrl)
 }
 
 template <int EPT>
-static void ms_expand_launch(hipStream_t s, int grid, const int32_t* Q, const int64_t* cumul,
-                             const int32_t* tile_k, const int64_t* off, const int32_t* col,
+static void ms_expand_launch(hipStream_t s, int grid, const int64_t* rowstart, const int32_t* uidv,
+                             const int64_t* cumul, const int32_t* tile_k, const int32_t* col,
                              const uint64_t* front, const uint64_t* seen, uint64_t* next,
                              const Ctrl* ctrl)
 {
-    hipLaunchKernelGGL(k_ms_expand<EPT>, dim3(grid), dim3(kWG), 0, s, Q, cumul, tile_k, off, col,
-                       front, seen, next, ctrl);
+    hipLaunchKernelGGL(k_ms_expand<EPT>, dim3(grid), dim3(kWG), 0, s, rowstart, uidv, cumul, tile_k,
+                       col, front, seen, next, ctrl);
 }
 
 int ms_expand_blocks_per_cu(int ept)
@@ -260,19 +262,20 @@ int ms_expand_blocks_per_cu(int ept)
 hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid, int ept,
                            int32_t V, int64_t tile_cap, const int64_t* off, const int32_t* col,
                            const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
-                           int64_t* bsum, int64_t* cumul, int32_t* tile_k, uint64_t* seen,
+                           int64_t* rowstart, int32_t* uidv, int64_t* bsum, int64_t* cumul,
+                           int32_t* tile_k, uint64_t* seen,
                            uint64_t* front, uint64_t* next, int16_t* const* lane_out,
                            const int32_t* lane_start, Ctrl* ctrl)
 {
-    hipError_t e = launch_scan_dev(s, scan_grid, Q, off, deg, bsum, cumul, tile_k, tile_cap,
-                                   kWG * ept, ctrl);
+    hipError_t e = launch_scan_dev(s, scan_grid, Q, off, nullptr, deg, rowstart, uidv, bsum, cumul,
+                                   tile_k, tile_cap, kWG * ept, ctrl);
     if (e != hipSuccess) return e;
     if (expand_grid < 1) expand_grid = 1;
     switch (ept) {
-    case 1: ms_expand_launch<1>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
-    case 2: ms_expand_launch<2>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
-    case 4: ms_expand_launch<4>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
-    case 8: ms_expand_launch<8>(s, expand_grid, Q, cumul, tile_k, off, col, front, seen, next, ctrl); break;
+    case 1: ms_expand_launch<1>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
+    case 2: ms_expand_launch<2>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
+    case 4: ms_expand_launch<4>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
+    case 8: ms_expand_launch<8>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
     default: return hipErrorInvalidValue;
     }
     if (fin_grid < 1) fin_grid = 1;

@@ -4,7 +4,8 @@
 // by degree bucket; vertices of degree >= kDegBuckets - 1 share the first
 // bucket, ties in arbitrary order).  The highest-degree vertices then own
 // the lowest ids, so the visited bits that most frontier edges probe sit in
-// a few contiguous words (see k_expand's LDS snapshot).  The relabelled CSR
+// a few contiguous words (and the visited summary's fully visited prefix
+// covers them after the first levels).  The relabelled CSR
 // keeps every row's neighbours in the input's order, mapped through rank.
 // Graph creation is not part of a search's timed region (the paper starts
 // its clock after partitioning the graph, Section 4).
@@ -97,10 +98,10 @@ __global__ __launch_bounds__(kWG) void k_deg_scatter(int32_t V, const int64_t* _
 // col_r[e] = rank[col[off[orig[x]] + j]] for the j-th entry of internal row
 // x, e = off_r[x] + j: the edge mapping of the search, with the identity
 // frontier Q = orig over all vertices.
-__global__ __launch_bounds__(kWG) void k_relabel_copy(const int32_t* __restrict__ orig,
+__global__ __launch_bounds__(kWG) void k_relabel_copy(const int64_t* __restrict__ rowstart,
+                                                      const int32_t* __restrict__ uidv,
                                                       const int64_t* __restrict__ off_r,
                                                       const int32_t* __restrict__ tile_k,
-                                                      const int64_t* __restrict__ off,
                                                       const int32_t* __restrict__ col,
                                                       const int32_t* __restrict__ rank,
                                                       int32_t* __restrict__ col_r,
@@ -109,11 +110,14 @@ __global__ __launch_bounds__(kWG) void k_relabel_copy(const int32_t* __restrict_
     __shared__ TileLds<kRelabelEPT> L;
     const int64_t r = ctrl->r;
     const int32_t ntiles = ctrl->ntiles;
+    StageRegs<kRelabelEPT> cur =
+        fetch_stage<kRelabelEPT>(blockIdx.x, ntiles, off_r, rowstart, uidv, tile_k);
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         int32_t uid[kRelabelEPT], v[kRelabelEPT];
         bool ok[kRelabelEPT];
         int64_t e[kRelabelEPT];
-        map_tile<kRelabelEPT>(L, tile, r, orig, off_r, tile_k, off, col, nullptr, uid, v, ok, e);
+        map_tile<kRelabelEPT>(L, cur, r, off_r, rowstart, uidv, col, uid, v, ok, e);
+        cur = fetch_stage<kRelabelEPT>(tile + gridDim.x, ntiles, off_r, rowstart, uidv, tile_k);
 #pragma unroll
         for (int j = 0; j < kRelabelEPT; ++j)
             if (ok[j]) col_r[e[j]] = rank[v[j]];
@@ -123,9 +127,9 @@ __global__ __launch_bounds__(kWG) void k_relabel_copy(const int32_t* __restrict_
 
 hipError_t build_degree_order(hipStream_t s, int32_t V, int64_t nnz, const int64_t* off,
                               const int32_t* col, int32_t* rank, int32_t* orig, int64_t* off_r,
-                              int32_t* col_r, int32_t* deg_tmp, int64_t* bsum_tmp,
-                              int32_t* tile_k, int64_t tile_cap, uint32_t* hist_tmp, Ctrl* ctrl,
-                              int grid_cap)
+                              int32_t* col_r, int32_t* deg_tmp, int64_t* rowstart_tmp,
+                              int32_t* uid_tmp, int64_t* bsum_tmp, int32_t* tile_k,
+                              int64_t tile_cap, uint32_t* hist_tmp, Ctrl* ctrl, int grid_cap)
 {
     hipError_t e = hipMemsetAsync(hist_tmp, 0, 2 * kDegBuckets * sizeof(uint32_t), s);
     if (e != hipSuccess) return e;
@@ -139,11 +143,11 @@ hipError_t build_degree_order(hipStream_t s, int32_t V, int64_t nnz, const int64
                        hist_tmp + kDegBuckets, rank, orig);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // off_r = exclusive scan of deg(orig[x]) with tile heads for the copy
-    e = launch_scan(s, orig, V, off, deg_tmp, bsum_tmp, off_r, tile_k, tile_cap,
-                    kWG * kRelabelEPT, (int64_t)1 << 62, 0, ctrl);
+    e = launch_scan(s, orig, V, off, nullptr, deg_tmp, rowstart_tmp, uid_tmp, bsum_tmp, off_r,
+                    tile_k, tile_cap, kWG * kRelabelEPT, (int64_t)1 << 62, 0, ctrl);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_relabel_copy, dim3((unsigned)grid_cap), dim3(kWG), 0, s, orig, off_r,
-                       tile_k, off, col, rank, col_r, ctrl);
+    hipLaunchKernelGGL(k_relabel_copy, dim3((unsigned)grid_cap), dim3(kWG), 0, s, rowstart_tmp,
+                       uid_tmp, off_r, tile_k, col, rank, col_r, ctrl);
     (void)nnz;
     return hipGetLastError();
 }

@@ -22,7 +22,7 @@ int ok();
 
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct WsLayout {
-    size_t vis, vis_old, q0, q1, deg, cumul, bsum, tile_k, ctrl, scratch, summary;
+    size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, summary;
     size_t ms_seen, ms_front, ms_next, ms_ctrl, ms_roots;
     size_t rank, orig, off_r, col_r, hist;
     size_t total;
@@ -49,6 +49,8 @@ struct bfs_graph {
     uint32_t* vis_old = nullptr;
     int32_t* q[2] = {nullptr, nullptr};
     int32_t* deg = nullptr;
+    int64_t* rowstart = nullptr;  // per frontier entry: row start in s_off
+    int32_t* suid = nullptr;      // per frontier entry: id reported as parent
     int64_t* cumul = nullptr;
     int64_t* bsum = nullptr;
     int32_t* tile_k = nullptr;
@@ -78,7 +80,7 @@ struct bfs_graph {
     hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing
 
     // options
-    int ept = 8;
+    int ept = 4;
     int frontier_mode = 0;  // 0 auto, 1 list only, 2 bitmap whenever possible
     int loop_driver = 0;    // 0 auto, 1 host, 2 device loop for small frontiers
     int batch_tile = 1024;  // edges per workgroup in the batch expansion

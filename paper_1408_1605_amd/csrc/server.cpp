@@ -112,6 +112,8 @@ struct SrvBatch {
     uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
     int32_t* q[2] = {nullptr, nullptr};
     int32_t* deg = nullptr;
+    int64_t* rowstart = nullptr;
+    int32_t* suid = nullptr;
     int64_t* cumul = nullptr;
     int64_t* bsum = nullptr;
     int32_t* tile_k = nullptr;
@@ -144,8 +146,8 @@ static size_t batch_state_bytes(const bfs_graph* g)
     const size_t nblk = (V + kScanChunk - 1) / kScanChunk;
     const size_t ntile = (size_t)((g->nnz + kMinTile - 1) / kMinTile);
     size_t b = 0;
-    b += 3 * align256(V * 8);
-    b += 3 * align256(V * 4);
+    b += 4 * align256(V * 8);
+    b += 4 * align256(V * 4);
     b += align256((V + 1) * 8);
     b += align256((nblk + 1) * 8);
     b += align256((ntile + 2) * 4);
@@ -185,7 +187,8 @@ hipError_t enqueue_srv_level(const bfs_graph* g, SrvBatch* B, hipStream_t s, int
     const int expand = g->num_cus * std::min(8, ms_expand_blocks_per_cu(ept));
     const int fin = g->num_cus * 4;
     return launch_ms_level(s, scan, expand, fin, ept, g->V, tile_cap, g->s_off, g->s_col, g->orig,
-                           B->q[parity], B->q[parity ^ 1], B->deg, B->bsum, B->cumul, B->tile_k,
+                           B->q[parity], B->q[parity ^ 1], B->deg, B->rowstart, B->suid, B->bsum,
+                           B->cumul, B->tile_k,
                            B->seen, B->front, B->next, B->lane_out, B->lane_start, B->ctrl);
 }
 
@@ -219,6 +222,8 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
         B->q[0] = (int32_t*)take(V * 4);
         B->q[1] = (int32_t*)take(V * 4);
         B->deg = (int32_t*)take(V * 4);
+        B->rowstart = (int64_t*)take(V * 8);
+        B->suid = (int32_t*)take(V * 4);
         B->cumul = (int64_t*)take((V + 1) * 8);
         B->bsum = (int64_t*)take(((V + kScanChunk - 1) / kScanChunk + 1) * 8);
         B->tile_k = (int32_t*)take((size_t)((g->nnz + kMinTile - 1) / kMinTile + 2) * 4);

@@ -1,9 +1,11 @@
 // Edge -> thread mapping of one tile of frontier edges (device code).
 //
-// The frontier entries Q[0..qlen) have an exclusive cumulative degree array
-// cumul; frontier edge e belongs to entry k = max{l : cumul[l] <= e} and is
-// the (e - cumul[k])-th neighbour of that entry's row (Section 3.4: the
-// mapping formula, read with the exclusive scan, and Algorithm 3).
+// The frontier entries k = 0..qlen-1 have an exclusive cumulative degree
+// array cumul; frontier edge e belongs to entry k = max{l : cumul[l] <= e}
+// and is the (e - cumul[k])-th neighbour of that entry's row (Section 3.4:
+// the mapping formula, read with the exclusive scan, and Algorithm 3).  The
+// degree scan also stores, per entry, its row start (rowstart[k]) and the id
+// reported as parent (uid[k]), so mapping a tile needs no dependent gathers.
 //
 // A workgroup owns the tile of TILE = 256 * EPT consecutive edges
 // [e0, e0 + TILE).  tile_k[t] is the entry holding edge t * TILE, so the
@@ -12,6 +14,9 @@
 // its first slot and then advances linearly over EPT consecutive slots
 // (Section 3.4.1), recording slot -> entry in LDS.  Edges are then read with
 // a slot stride of 256 so a wave's 64 column loads are contiguous.
+//
+// A tile's staging entries are fetched into registers one tile ahead
+// (fetch_stage), so their latency overlaps the previous tile's probes.
 #pragma once
 
 #include "bfs_internal.h"
@@ -25,45 +30,83 @@ template <int EPT>
 struct TileLds {
     static constexpr int TILE = kWG * EPT;
     static constexpr int CAP = TILE / 2;
+    static constexpr int PER = (CAP + 1 + kWG - 1) / kWG;  // entries per thread
     int32_t cum[CAP + 1];
     int32_t uid[CAP + 1];     // id reported for the entry (parent value)
     int64_t base[CAP + 1];    // row start minus cumulative degree
     uint16_t map[TILE];
 };
 
-// Fills, for j < EPT, the edge slot threadIdx.x + j * 256 of tile `tile`:
-// ok[j] (slot is a real edge), uid[j] (the entry's id, mapped through
-// uid_map when it is not null), col_val[j] (the neighbour read from col) and
-// eidx[j] (the global edge index).  Every thread of the workgroup must call
-// it (it contains barriers); the caller must barrier before reusing L.
 template <int EPT>
-__device__ __forceinline__ void map_tile(TileLds<EPT>& L, int32_t tile, int64_t r,
-                                         const int32_t* __restrict__ Q,
+struct StageRegs {
+    int32_t tile, k_lo, k_hi;
+    int64_t cum[TileLds<EPT>::PER];
+    int64_t rs[TileLds<EPT>::PER];
+    int32_t uid[TileLds<EPT>::PER];
+};
+
+// Issue the loads of tile `tile`'s staging entries (tile < 0: nothing).
+template <int EPT>
+__device__ __forceinline__ StageRegs<EPT> fetch_stage(int32_t tile, int32_t ntiles,
+                                                      const int64_t* __restrict__ cumul,
+                                                      const int64_t* __restrict__ rowstart,
+                                                      const int32_t* __restrict__ uidv,
+                                                      const int32_t* __restrict__ tile_k)
+{
+    StageRegs<EPT> R;
+    R.tile = tile < ntiles ? tile : -1;
+    R.k_lo = 0;
+    R.k_hi = -1;
+    if (R.tile < 0) return R;
+    R.k_lo = tile_k[tile];
+    R.k_hi = tile_k[tile + 1];
+    const int32_t n_k = R.k_hi - R.k_lo + 1;
+    if (n_k <= TileLds<EPT>::CAP + 1) {
+#pragma unroll
+        for (int m = 0; m < TileLds<EPT>::PER; ++m) {
+            const int32_t i = threadIdx.x + m * kWG;
+            if (i < n_k) {
+                const int32_t k = R.k_lo + i;
+                R.cum[m] = cumul[k];
+                R.rs[m] = rowstart[k];
+                R.uid[m] = uidv[k];
+            }
+        }
+    }
+    return R;
+}
+
+// Map tile R.tile and load its column values: for j < EPT, slot
+// threadIdx.x + j * 256 gives ok[j] (a real edge), uid[j] (the entry's
+// reported id), col_val[j] (the neighbour) and eidx[j] (the edge index).
+// Every thread of the workgroup must call it (it contains barriers); the
+// caller must barrier before the next call reuses L.
+template <int EPT>
+__device__ __forceinline__ void map_tile(TileLds<EPT>& L, const StageRegs<EPT>& R, int64_t r,
                                          const int64_t* __restrict__ cumul,
-                                         const int32_t* __restrict__ tile_k,
-                                         const int64_t* __restrict__ off,
+                                         const int64_t* __restrict__ rowstart,
+                                         const int32_t* __restrict__ uidv,
                                          const int32_t* __restrict__ col,
-                                         const int32_t* __restrict__ uid_map,
                                          int32_t uid[EPT], int32_t col_val[EPT], bool ok[EPT],
                                          int64_t eidx[EPT])
 {
     constexpr int TILE = TileLds<EPT>::TILE;
-    const int64_t e0 = (int64_t)tile * TILE;
+    const int64_t e0 = (int64_t)R.tile * TILE;
     const int64_t rem = r - e0;
     const int32_t n_e = rem < TILE ? (int32_t)rem : TILE;
-    const int32_t k_lo = tile_k[tile];
-    const int32_t k_hi = tile_k[tile + 1];
+    const int32_t k_lo = R.k_lo, k_hi = R.k_hi;
     const int32_t n_k = k_hi - k_lo + 1;
 
     if (n_k <= TileLds<EPT>::CAP + 1) {
-        for (int32_t i = threadIdx.x; i < n_k; i += kWG) {
-            const int32_t k = k_lo + i;
-            const int32_t x = Q[k];
-            const int64_t c = cumul[k];
-            const int64_t rel = c - e0;
-            L.cum[i] = rel > 0 ? (int32_t)rel : 0;
-            L.uid[i] = uid_map ? uid_map[x] : x;
-            L.base[i] = off[x] - c;
+#pragma unroll
+        for (int m = 0; m < TileLds<EPT>::PER; ++m) {
+            const int32_t i = threadIdx.x + m * kWG;
+            if (i < n_k) {
+                const int64_t rel = R.cum[m] - e0;
+                L.cum[i] = rel > 0 ? (int32_t)rel : 0;
+                L.uid[i] = R.uid[m];
+                L.base[i] = R.rs[m] - R.cum[m];
+            }
         }
         __syncthreads();
         const int32_t s0 = threadIdx.x * EPT;
@@ -116,9 +159,8 @@ __device__ __forceinline__ void map_tile(TileLds<EPT>& L, int32_t tile, int64_t 
                     if (cumul[mid] <= e) lo = mid;
                     else hi = mid - 1;
                 }
-                const int32_t x = Q[lo];
-                uid[j] = uid_map ? uid_map[x] : x;
-                col_val[j] = col[off[x] + (e - cumul[lo])];
+                uid[j] = uidv[lo];
+                col_val[j] = col[rowstart[lo] + (e - cumul[lo])];
             }
         }
     }

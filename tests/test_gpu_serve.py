@@ -115,7 +115,7 @@ def test_serve_budget_queues(bfsmi, pool):
     def al(x):
         return (x + 255) // 256 * 256
     V = g.V
-    state = (3 * al(8 * V) + 3 * al(4 * V) + al(8 * (V + 1)) + al(8 * ((V + 2047) // 2048 + 1))
+    state = (4 * al(8 * V) + 4 * al(4 * V) + al(8 * (V + 1)) + al(8 * ((V + 2047) // 2048 + 1))
              + al(4 * ((g.nnz + 255) // 256 + 2)) + al(128) + al(512) + al(256) + al(512))
     s, ids, arena = make_server(bfsmi, [h], arena_bytes=state + 3 * al(2 * V) + 256)
     roots = graphgen.pick_roots(g, 40, 5)
@@ -129,7 +129,8 @@ def test_serve_budget_queues(bfsmi, pool):
 
 def test_serve_never_fits(bfsmi, pool):
     graphs, handles = pool
-    arena = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    # the scale-14 graph needs ~1 MB of batch state; give it 256 KB
+    arena = torch.empty(256 << 10, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     s = bfsmi.bfs_server_create(arena)
     with pytest.raises(bfsmi.BFSError) as e:
