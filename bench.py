@@ -59,6 +59,37 @@ def cpu_model():
     return platform.processor()
 
 
+def kernel_source_hash():
+    """Hash of the sources that define the expansion kernel; counter-derived
+    traffic is only reported while it matches the hash recorded with it."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("frontier.hip", "tile_map.h", "wave_ops.h", "bfs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1408_1605_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel_hash):
+    """HBM bytes per expansion launch from profiles/k_expand_rmat26_traffic.txt
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None."""
+    path = os.path.join(ROOT, "profiles", "k_expand_rmat26_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_hash:
+        return None
+    try:
+        return int(float(vals["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def single_root(args, torch, np, graphgen, bfsmi):
     t = time.time()
     g = graphgen.rmat(args.scale)
@@ -123,7 +154,9 @@ def single_root(args, torch, np, graphgen, bfsmi):
         "ms_per_step": total * 1e3 / args.steps,
         "median_gteps": sorted(teps)[len(teps) // 2],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(kernel_source_hash()),
+                     "source_hash": kernel_source_hash(),
                      "kernel": "k_expand<%d>" % bfsmi.bfs_get_option(G.handle, bfsmi.BFS_OPT_EDGES_PER_THREAD),
                      "launches": x_launch,
                      "avg_launch_ms": round(x_ms / max(x_launch, 1), 5),
@@ -284,6 +317,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-arena-gb", type=int, default=48)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -303,6 +338,15 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 1 << 28  # int32 elements: 1 GiB read + 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        return
     res, g = single_root(args, torch, np, graphgen, bfsmi)
     batch = None if args.no_batch else batch_section(args, torch, np, graphgen, bfsmi)
     serve = None if args.no_serve else serve_section(args, torch, np, graphgen, bfsmi)

@@ -68,6 +68,7 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
         L.ms_next = take((size_t)V * 8);
         L.ms_ctrl = take(sizeof(Ctrl));
         L.ms_roots = take(64 * 4);
+        L.ms_touched = take(W * 4);
     }
     if (flags & BFS_DEGREE_ORDER) {
         L.rank = take((size_t)V * 4);
@@ -176,6 +177,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         g->ms_next = reinterpret_cast<uint64_t*>(g->ws + L.ms_next);
         g->ms_ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ms_ctrl);
         g->ms_roots = reinterpret_cast<int32_t*>(g->ws + L.ms_roots);
+        g->ms_touched = reinterpret_cast<uint32_t*>(g->ws + L.ms_touched);
     }
 
     auto cleanup = [&](int code) {

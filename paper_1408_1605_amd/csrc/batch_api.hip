@@ -47,8 +47,8 @@ static hipError_t enqueue_level(bfs_graph* g, hipStream_t s, const BatchGrids& b
     return launch_ms_level(s, b.scan, b.expand, b.fin, b.ept, g->V, b.tile_cap, g->s_off, g->s_col,
                            g->orig, g->q[parity], g->q[parity ^ 1], g->deg, g->rowstart, g->suid,
                            g->bsum, g->cumul,
-                           g->tile_k, g->ms_seen, g->ms_front, g->ms_next, nullptr, nullptr,
-                           g->ms_ctrl);
+                           g->tile_k, g->ms_seen, g->ms_front, g->ms_next, g->ms_touched, nullptr,
+                           nullptr, g->ms_ctrl);
 }
 
 static int capture_batch_graph(bfs_graph* g, const BatchGrids& b)
@@ -141,7 +141,8 @@ extern "C" int bfs_run_batch(bfs_graph* g, const int32_t* h_roots, int32_t n_roo
     BFS_HIP_TRY(hipMemcpyAsync(g->ms_roots, g->h_roots, sizeof(int32_t) * (size_t)n_roots,
                                hipMemcpyHostToDevice, s));
     BFS_HIP_TRY(launch_ms_init(s, g->num_cus * 8, g->V, g->ms_roots, n_roots, g->rank, g->ms_seen,
-                               g->ms_front, g->ms_next, d_levels, g->q[0], g->ms_ctrl));
+                               g->ms_front, g->ms_next, g->ms_touched, d_levels, g->q[0],
+                               g->ms_ctrl));
     const bool use_graph = g->loop_driver != 1;
     if (use_graph) {
         rc = capture_batch_graph(g, b);

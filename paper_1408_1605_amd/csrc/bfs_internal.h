@@ -31,7 +31,9 @@ struct alignas(64) Ctrl {
     int32_t err;         // set when a guard trips (never expected)
     int32_t full_prefix; // every id below it is visited (visited summary)
     int32_t overflow;    // batch: a level did not fit the output type
-    int32_t pad;
+    int32_t sparse;      // batch: this level's union frontier is small (see msbfs.hip)
+    int32_t sparse_limit;  // batch: frontier sizes up to this count as small
+    int32_t pad2;
     uint64_t alive;      // batch: OR of the lanes that found vertices this level
     uint64_t last_alive; // batch: alive of the last completed level
     int8_t* out8;        // batch: output rows (read by the device each launch)
@@ -88,21 +90,23 @@ hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
 // their sizes from ctrl and return at once when ctrl->done is set.
 hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* h_roots_dev,
                           int32_t n_roots, const int32_t* rank, uint64_t* seen, uint64_t* front,
-                          uint64_t* next, int8_t* out8, int32_t* Q, Ctrl* ctrl);
+                          uint64_t* next, uint32_t* touched, int8_t* out8, int32_t* Q,
+                          Ctrl* ctrl);
 hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid,
                            int ept, int32_t V, int64_t tile_cap, const int64_t* off,
                            const int32_t* col, const int32_t* orig, const int32_t* Q,
                            int32_t* Qn, int32_t* deg, int64_t* rowstart, int32_t* uidv,
                            int64_t* bsum, int64_t* cumul,
                            int32_t* tile_k, uint64_t* seen, uint64_t* front, uint64_t* next,
-                           int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl);
+                           uint32_t* touched, int16_t* const* lane_out,
+                           const int32_t* lane_start, Ctrl* ctrl);
 int ms_expand_blocks_per_cu(int ept);
 
 // Serving lanes (msbfs.hip).  lane_out: device table of 64 int16 result
 // pointers; lane_start: device int32[64]; join: device int32 pairs
 // (root, lane).
 hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t* front,
-                            uint64_t* next, Ctrl* ctrl);
+                            uint64_t* next, uint32_t* touched, Ctrl* ctrl);
 hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t mask);
 hipError_t launch_fill16(hipStream_t s, int grid, int16_t* p, int64_t n, int16_t val);
 hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32_t* join,

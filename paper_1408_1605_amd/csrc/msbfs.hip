@@ -7,10 +7,16 @@
 // frontier {v : front[v] != 0}: the same degree scan and edge -> thread
 // mapping, with the visited test and claim done on whole masks,
 //   next[v] |= front[u] & ~seen[v]   (64-bit atomic OR, no return value),
-// then a dense pass turns next into the new frontier (new = next & ~seen),
+// then a finalize pass turns next into the new frontier (new = next & ~seen),
 // writes level L into row b of the output for every new lane b, and
 // compacts the union frontier.  Lanes never interact, so each row equals the
 // single-root search from its root.
+//
+// When the union frontier is small (at most V/64 vertices: deep, narrow
+// searches such as grids), the expansion also marks each vertex it finds in
+// a touched bitmap, the old frontier's masks are cleared through the queue,
+// and the finalize pass only does work for touched vertices, so a level
+// costs O(frontier + V/32) instead of O(V).
 //
 // Every launch reads its sizes from ctrl and returns at once when
 // ctrl->done is set, so a fixed sequence of levels can be captured in a
@@ -25,6 +31,7 @@ __global__ __launch_bounds__(kWG) void k_ms_clear(int32_t V, int32_t n_roots,
                                                   uint64_t* __restrict__ seen,
                                                   uint64_t* __restrict__ front,
                                                   uint64_t* __restrict__ next,
+                                                  uint32_t* __restrict__ touched,
                                                   int8_t* __restrict__ out8, int vec)
 {
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -34,6 +41,7 @@ __global__ __launch_bounds__(kWG) void k_ms_clear(int32_t V, int32_t n_roots,
         front[v] = 0;
         next[v] = 0;
     }
+    for (int64_t w = tid; w < ((int64_t)V + 31) / 32; w += stride) touched[w] = 0;
     const int64_t nbytes = (int64_t)n_roots * V;
     int64_t done = 0;
     if (vec) {
@@ -96,17 +104,19 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
         ctrl->alive = 0;
         ctrl->last_alive = 0;
         ctrl->out8 = out8;
+        ctrl->sparse_limit = V / 64;
+        ctrl->sparse = s_n <= V / 64;
     }
 }
 
 hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* roots_dev,
                           int32_t n_roots, const int32_t* rank, uint64_t* seen, uint64_t* front,
-                          uint64_t* next, int8_t* out8, int32_t* Q, Ctrl* ctrl)
+                          uint64_t* next, uint32_t* touched, int8_t* out8, int32_t* Q, Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
     const int vec = ((uintptr_t)out8 % 16) == 0;
-    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, n_roots, seen, front, next, out8,
-                       vec);
+    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, n_roots, seen, front, next,
+                       touched, out8, vec);
     hipLaunchKernelGGL(k_ms_roots, dim3(1), dim3(64), 0, s, V, n_roots, roots_dev, rank, seen, front,
                        out8, Q, ctrl);
     return hipGetLastError();
@@ -121,10 +131,12 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(const int64_t* __restrict__ r
                                                    const uint64_t* __restrict__ front,
                                                    const uint64_t* __restrict__ seen,
                                                    uint64_t* __restrict__ next,
+                                                   uint32_t* __restrict__ touched,
                                                    const Ctrl* __restrict__ ctrl)
 {
     __shared__ TileLds<EPT> L;
     if (ctrl->done) return;
+    const bool sparse = ctrl->sparse != 0;
     const int64_t r = ctrl->r;
     const int32_t ntiles = ctrl->ntiles;
     StageRegs<EPT> cur = fetch_stage<EPT>(blockIdx.x, ntiles, cumul, rowstart, uidv, tile_k);
@@ -142,8 +154,13 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(const int64_t* __restrict__ r
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const uint64_t nb = f[j] & ~sn[j];
-            if (nb) (void)__hip_atomic_fetch_or(next + vv[j], nb, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
+            if (nb) {
+                (void)__hip_atomic_fetch_or(next + vv[j], nb, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+                if (sparse)
+                    (void)__hip_atomic_fetch_or(touched + (vv[j] >> 5), 1u << (vv[j] & 31),
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         __syncthreads();
     }
@@ -163,6 +180,7 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
                                                      uint64_t* __restrict__ seen,
                                                      uint64_t* __restrict__ front,
                                                      uint64_t* __restrict__ next,
+                                                     uint32_t* __restrict__ touched,
                                                      int32_t* __restrict__ Qn,
                                                      int16_t* const* __restrict__ lane_out,
                                                      const int32_t* __restrict__ lane_start,
@@ -170,13 +188,21 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
 {
     if (ctrl->done) return;
     const int32_t lvl = ctrl->level;
+    const bool sparse = ctrl->sparse != 0;
     int8_t* __restrict__ out8 = ctrl->out8;
     const int64_t stride = (int64_t)gridDim.x * kWG;
     uint64_t alive = 0;
     for (int64_t base = (int64_t)blockIdx.x * kWG; base < V; base += stride) {
         const int64_t v = base + threadIdx.x;
         uint64_t nw = 0;
-        if (v < V) {
+        bool hit = v < V;
+        if (sparse && v < V) {
+            // the 32 lanes of a word read it before its first lane clears it
+            const uint32_t tw = touched[v >> 5];
+            hit = (tw >> (v & 31)) & 1u;
+            if ((v & 31) == 0 && tw) touched[v >> 5] = 0;
+        }
+        if (hit) {
             const uint64_t n = next[v];
             if (n) {
                 const uint64_t sv = seen[v];
@@ -220,10 +246,23 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
     if (__lane_id() == 0 && alive) atomicOr((unsigned long long*)&ctrl->alive, (unsigned long long)alive);
 }
 
+// Sparse levels: the old frontier's masks are cleared through the queue
+// (after the expansion has read them, before the finalize writes new ones).
+__global__ __launch_bounds__(kWG) void k_ms_clear_front(const int32_t* __restrict__ Q,
+                                                        uint64_t* __restrict__ front,
+                                                        const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl->done || !ctrl->sparse) return;
+    const int32_t qlen = ctrl->qlen;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < qlen; k += stride) front[Q[k]] = 0;
+}
+
 __global__ void k_ms_advance(Ctrl* __restrict__ ctrl)
 {
     if (ctrl->done) return;
     const uint32_t q = ctrl->qn_count;
+    ctrl->sparse = (int32_t)q <= ctrl->sparse_limit;
     ctrl->last_alive = ctrl->alive;  // lanes that found vertices this level
     ctrl->alive = 0;
     ctrl->reached += q;
@@ -238,10 +277,10 @@ template <int EPT>
 static void ms_expand_launch(hipStream_t s, int grid, const int64_t* rowstart, const int32_t* uidv,
                              const int64_t* cumul, const int32_t* tile_k, const int32_t* col,
                              const uint64_t* front, const uint64_t* seen, uint64_t* next,
-                             const Ctrl* ctrl)
+                             uint32_t* touched, const Ctrl* ctrl)
 {
     hipLaunchKernelGGL(k_ms_expand<EPT>, dim3(grid), dim3(kWG), 0, s, rowstart, uidv, cumul, tile_k,
-                       col, front, seen, next, ctrl);
+                       col, front, seen, next, touched, ctrl);
 }
 
 int ms_expand_blocks_per_cu(int ept)
@@ -264,27 +303,28 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
                            const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
                            int64_t* rowstart, int32_t* uidv, int64_t* bsum, int64_t* cumul,
                            int32_t* tile_k, uint64_t* seen,
-                           uint64_t* front, uint64_t* next, int16_t* const* lane_out,
-                           const int32_t* lane_start, Ctrl* ctrl)
+                           uint64_t* front, uint64_t* next, uint32_t* touched,
+                           int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl)
 {
     hipError_t e = launch_scan_dev(s, scan_grid, Q, off, nullptr, deg, rowstart, uidv, bsum, cumul,
                                    tile_k, tile_cap, kWG * ept, ctrl);
     if (e != hipSuccess) return e;
     if (expand_grid < 1) expand_grid = 1;
     switch (ept) {
-    case 1: ms_expand_launch<1>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
-    case 2: ms_expand_launch<2>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
-    case 4: ms_expand_launch<4>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
-    case 8: ms_expand_launch<8>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, ctrl); break;
+    case 1: ms_expand_launch<1>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
+    case 2: ms_expand_launch<2>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
+    case 4: ms_expand_launch<4>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
+    case 8: ms_expand_launch<8>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
     default: return hipErrorInvalidValue;
     }
     if (fin_grid < 1) fin_grid = 1;
+    hipLaunchKernelGGL(k_ms_clear_front, dim3(scan_grid), dim3(kWG), 0, s, Q, front, ctrl);
     if (lane_out) {
         hipLaunchKernelGGL(k_ms_finalize<true>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, seen,
-                           front, next, Qn, lane_out, lane_start, ctrl);
+                           front, next, touched, Qn, lane_out, lane_start, ctrl);
     } else {
         hipLaunchKernelGGL(k_ms_finalize<false>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, seen,
-                           front, next, Qn, lane_out, lane_start, ctrl);
+                           front, next, touched, Qn, lane_out, lane_start, ctrl);
     }
     hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ctrl);
     return hipGetLastError();
@@ -297,6 +337,7 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
 __global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, uint64_t* __restrict__ seen,
                                                    uint64_t* __restrict__ front,
                                                    uint64_t* __restrict__ next,
+                                                   uint32_t* __restrict__ touched,
                                                    Ctrl* __restrict__ ctrl)
 {
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -305,6 +346,8 @@ __global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, uint64_t* __restri
         front[v] = 0;
         next[v] = 0;
     }
+    for (int64_t w = (int64_t)blockIdx.x * kWG + threadIdx.x; w < ((int64_t)V + 31) / 32; w += stride)
+        touched[w] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->qlen = 0;
         ctrl->qn_count = 0;
@@ -320,6 +363,8 @@ __global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, uint64_t* __restri
         ctrl->alive = 0;
         ctrl->last_alive = 0;
         ctrl->out8 = nullptr;
+        ctrl->sparse_limit = V / 64;
+        ctrl->sparse = 1;
     }
 }
 
@@ -373,14 +418,16 @@ __global__ void k_srv_join(int32_t V, int32_t n_join, const int32_t* __restrict_
     __syncthreads();
     if (i == 0) {
         ctrl->qlen = qlen + s_app;
+        ctrl->sparse = ctrl->qlen <= ctrl->sparse_limit;
         ctrl->done = 0;
     }
 }
 
 hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t* front,
-                            uint64_t* next, Ctrl* ctrl)
+                            uint64_t* next, uint32_t* touched, Ctrl* ctrl)
 {
-    hipLaunchKernelGGL(k_srv_reset, dim3(grid), dim3(kWG), 0, s, V, seen, front, next, ctrl);
+    hipLaunchKernelGGL(k_srv_reset, dim3(grid), dim3(kWG), 0, s, V, seen, front, next, touched,
+                       ctrl);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ int ok();
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct WsLayout {
     size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, summary;
-    size_t ms_seen, ms_front, ms_next, ms_ctrl, ms_roots;
+    size_t ms_seen, ms_front, ms_next, ms_ctrl, ms_roots, ms_touched;
     size_t rank, orig, off_r, col_r, hist;
     size_t total;
 };
@@ -63,6 +63,7 @@ struct bfs_graph {
     uint64_t* ms_next = nullptr;
     bfsmi::Ctrl* ms_ctrl = nullptr;
     int32_t* ms_roots = nullptr;       // device copy of the batch roots (64)
+    uint32_t* ms_touched = nullptr;    // batch: vertices found this level (sparse levels)
 
     // the CSR the search runs on: the caller's, or the degree-ordered copy
     const int64_t* s_off = nullptr;

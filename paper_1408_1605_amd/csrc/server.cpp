@@ -110,6 +110,7 @@ struct SrvQuery {
 struct SrvBatch {
     char* mem = nullptr;
     uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
+    uint32_t* touched = nullptr;
     int32_t* q[2] = {nullptr, nullptr};
     int32_t* deg = nullptr;
     int64_t* rowstart = nullptr;
@@ -124,9 +125,14 @@ struct SrvBatch {
     uint64_t lane_ticket[64] = {};
     int64_t lane_age[64] = {};     // levels run since the lane joined
     uint64_t active = 0;
-    int parity = 0;
+    int parity = 0;                // stays 0: every replay runs an even number of levels
     bool in_flight = false;
+    int64_t idle_since = 0;        // steady-clock ns when the batch went idle (0: busy)
+    hipGraphExec_t round[3] = {nullptr, nullptr, nullptr};  // 2, 8, 32 levels
 };
+
+constexpr int kRoundLevels[3] = {2, 8, 32};
+constexpr int64_t kIdleKeepNs = 100 * 1000 * 1000;  // idle batches kept 100 ms
 
 struct SrvGraph {
     bfs_graph* g = nullptr;
@@ -147,6 +153,7 @@ static size_t batch_state_bytes(const bfs_graph* g)
     const size_t ntile = (size_t)((g->nnz + kMinTile - 1) / kMinTile);
     size_t b = 0;
     b += 4 * align256(V * 8);
+    b += align256((V + 31) / 32 * 4);
     b += 4 * align256(V * 4);
     b += align256((V + 1) * 8);
     b += align256((nblk + 1) * 8);
@@ -179,17 +186,53 @@ struct bfs_server {
 
 namespace {
 
+int clampi(int64_t x, int lo, int hi) { return (int)std::max<int64_t>(lo, std::min<int64_t>(x, hi)); }
+
 hipError_t enqueue_srv_level(const bfs_graph* g, SrvBatch* B, hipStream_t s, int parity)
 {
+    // grids sized by the graph: every kernel is grid-stride, so this only
+    // trades idle workgroups on small graphs against parallelism on big ones
     const int ept = std::max(1, g->batch_tile / kWG);
     const int64_t tile_cap = (g->nnz + kMinTile - 1) / kMinTile + 1;
-    const int scan = g->num_cus * 2;
-    const int expand = g->num_cus * std::min(8, ms_expand_blocks_per_cu(ept));
-    const int fin = g->num_cus * 4;
+    const int scan = clampi(g->V / 8192, 8, g->num_cus * 2);
+    const int expand = clampi(g->nnz / 4096, 16, g->num_cus * std::min(8, ms_expand_blocks_per_cu(ept)));
+    const int fin = clampi(g->V / 4096, 8, g->num_cus * 4);
     return launch_ms_level(s, scan, expand, fin, ept, g->V, tile_cap, g->s_off, g->s_col, g->orig,
                            B->q[parity], B->q[parity ^ 1], B->deg, B->rowstart, B->suid, B->bsum,
-                           B->cumul, B->tile_k,
-                           B->seen, B->front, B->next, B->lane_out, B->lane_start, B->ctrl);
+                           B->cumul, B->tile_k, B->seen, B->front, B->next, B->touched,
+                           B->lane_out, B->lane_start, B->ctrl);
+}
+
+// Capture kRoundLevels[i] levels of this batch into round[i].
+int capture_rounds(const bfs_graph* g, SrvBatch* B, hipStream_t s)
+{
+    for (int i = 0; i < 3; ++i) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return BFS_ERR_HIP;
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < kRoundLevels[i] && e == hipSuccess; ++k) e = enqueue_srv_level(g, B, s, k & 1);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e == hipSuccess && e2 == hipSuccess)
+            e = hipGraphInstantiate(&B->round[i], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            B->round[i] = nullptr;
+            return BFS_ERR_HIP;
+        }
+    }
+    return BFS_OK;
+}
+
+void free_batch(Arena& arena, SrvGraph& G)
+{
+    SrvBatch* B = G.batch;
+    if (!B) return;
+    (void)hipStreamSynchronize(G.stream);
+    for (auto& r : B->round)
+        if (r) (void)hipGraphExecDestroy(r);
+    arena.release(B->mem);
+    delete B;
+    G.batch = nullptr;
 }
 
 }  // namespace
@@ -203,9 +246,15 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
     if (!B) {
         if (G.pending.empty()) return false;
         int running = 0;
-        for (const auto& o : graphs) running += o.batch != nullptr;
+        for (const auto& o : graphs) running += o.batch != nullptr && o.batch->idle_since == 0;
         if (running >= cfg.max_inflight) return false;
         char* mem = arena.alloc(G.state_bytes);
+        if (!mem) {
+            // release idle batches of other graphs, then retry once
+            for (auto& o : graphs)
+                if (o.batch && o.batch->idle_since != 0) free_batch(arena, o);
+            mem = arena.alloc(G.state_bytes);
+        }
         if (!mem) return false;  // over budget: wait for memory to free up
         B = new SrvBatch();
         B->mem = mem;
@@ -219,6 +268,7 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
         B->seen = (uint64_t*)take(V * 8);
         B->front = (uint64_t*)take(V * 8);
         B->next = (uint64_t*)take(V * 8);
+        B->touched = (uint32_t*)take((V + 31) / 32 * 4);
         B->q[0] = (int32_t*)take(V * 4);
         B->q[1] = (int32_t*)take(V * 4);
         B->deg = (int32_t*)take(V * 4);
@@ -232,9 +282,10 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
         B->lane_start = (int32_t*)take(64 * 4);
         B->join = (int32_t*)take(128 * 4);
         G.batch = B;
-        if (launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->ctrl) !=
+        if (launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->touched, B->ctrl) !=
             hipSuccess)
             worker_err = BFS_ERR_HIP;
+        if (capture_rounds(g, B, G.stream) != BFS_OK) worker_err = BFS_ERR_HIP;
     }
     if (B->in_flight) {
         if (hipEventQuery(G.ev) != hipSuccess) return false;
@@ -256,7 +307,7 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
         B->active &= ~retired;
         if (retired) {
             if (c.err || c.overflow) {
-                (void)launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->ctrl);
+                (void)launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->touched, B->ctrl);
             } else {
                 (void)launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->seen, retired);
             }
@@ -297,22 +348,21 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
             worker_err = BFS_ERR_HIP;
     }
     if (!B->active) {
-        // nothing running and nothing admitted: release the batch
-        if (hipStreamSynchronize(G.stream) != hipSuccess) worker_err = BFS_ERR_HIP;
-        arena.release(B->mem);
-        delete B;
-        G.batch = nullptr;
+        // nothing running: keep the batch a little for the next query, then
+        // release its arena memory
+        const int64_t t = now_ns();
+        if (B->idle_since == 0) B->idle_since = t;
+        if (t - B->idle_since > kIdleKeepNs) free_batch(arena, G);
         return false;
     }
-    // levels per round: 1 while every lane is young, more for deep searches
+    B->idle_since = 0;
+    // levels per replay: 2 while every lane is young, more for deep searches
     int64_t oldest = 0;
     for (int b = 0; b < 64; ++b)
         if ((B->active >> b) & 1ull) oldest = std::max(oldest, B->lane_age[b]);
-    const int K = oldest < 32 ? 1 : (oldest < 256 ? 4 : 16);
-    for (int k = 0; k < K; ++k) {
-        if (enqueue_srv_level(g, B, G.stream, B->parity) != hipSuccess) worker_err = BFS_ERR_HIP;
-        B->parity ^= 1;
-    }
+    const int ri = oldest < 32 ? 0 : (oldest < 256 ? 1 : 2);
+    const int K = kRoundLevels[ri];
+    if (!B->round[ri] || hipGraphLaunch(B->round[ri], G.stream) != hipSuccess) worker_err = BFS_ERR_HIP;
     for (int b = 0; b < 64; ++b)
         if ((B->active >> b) & 1ull) B->lane_age[b] += K;
     if (hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, G.stream) !=
@@ -501,10 +551,7 @@ int bfs_server_destroy(bfs_server* s)
     (void)hipSetDevice(s->device);
     for (auto& G : s->graphs) {
         if (G.stream) (void)hipStreamSynchronize(G.stream);
-        if (G.batch) {
-            s->arena.release(G.batch->mem);
-            delete G.batch;
-        }
+        free_batch(s->arena, G);
         if (G.stream) (void)hipStreamDestroy(G.stream);
         if (G.ev) (void)hipEventDestroy(G.ev);
         if (G.h_ctrl) (void)hipHostFree(G.h_ctrl);

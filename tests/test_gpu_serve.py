@@ -115,7 +115,7 @@ def test_serve_budget_queues(bfsmi, pool):
     def al(x):
         return (x + 255) // 256 * 256
     V = g.V
-    state = (4 * al(8 * V) + 4 * al(4 * V) + al(8 * (V + 1)) + al(8 * ((V + 2047) // 2048 + 1))
+    state = (4 * al(8 * V) + al((V + 31) // 32 * 4) + 4 * al(4 * V) + al(8 * (V + 1)) + al(8 * ((V + 2047) // 2048 + 1))
              + al(4 * ((g.nnz + 255) // 256 + 2)) + al(128) + al(512) + al(256) + al(512))
     s, ids, arena = make_server(bfsmi, [h], arena_bytes=state + 3 * al(2 * V) + 256)
     roots = graphgen.pick_roots(g, 40, 5)
