@@ -14,6 +14,7 @@ The JSON line also carries:
                   against the MI355X HBM peak of 8 TB/s;
   cpu_baseline -- the serial CPU oracle on one root of the same graph, on
                   this host's cores (one thread), in GTEPS;
+  grid         -- single-root searches on the 4096 x 4096 grid (GTEPS);
   batch        -- 64 roots in one multi-source batch on R-MAT scale 22:
                   roots/s, and the speedup over 64 one-at-a-time searches;
   serve        -- open-loop Poisson queries (2000/s) over 32 resident graphs
@@ -190,6 +191,38 @@ def single_root(args, torch, np, graphgen, bfsmi):
     return res, g
 
 
+def grid_section(args, torch, np, graphgen, bfsmi):
+    """Single-root searches on the 4096 x 4096 4-neighbour grid (thousands
+    of narrow levels): GTEPS and levels, 16 seeded roots."""
+    w = args.grid_side
+    g = graphgen.grid(w)
+    rng = np.random.default_rng(2000 + w)
+    roots = [int(x) for x in rng.choice(g.V, size=args.grid_roots, replace=False)]
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    lv = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    pa = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    bfsmi.bfs_run(G.handle, roots[0], lv, pa)
+    torch.cuda.synchronize()
+    r0, c0 = divmod(roots[0], w)
+    rr, cc = np.divmod(np.arange(g.V, dtype=np.int64), w)
+    ok = bool(np.array_equal(lv.cpu().numpy(), np.abs(rr - r0) + np.abs(cc - c0)))
+    teps, levels, times = [], [], []
+    for r in roots:
+        t0 = time.perf_counter()
+        st = bfsmi.bfs_run(G.handle, r, lv, pa)
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        teps.append(st.edges_scanned / 2 / dt / 1e9)
+        levels.append(st.levels)
+    G.close()
+    res = {"graph": "grid%dx%d" % (w, w), "roots": len(roots), "gteps": round(harmonic_mean(teps), 4),
+           "ms_per_root": round(1e3 * sum(times) / len(times), 2),
+           "levels_min": int(min(levels)), "levels_max": int(max(levels)),
+           "root0_matches_manhattan": ok}
+    log("grid: %s" % res)
+    return res
+
+
 def batch_section(args, torch, np, graphgen, bfsmi):
     """64 roots in one bfs_run_batch on R-MAT scale 22 vs 64 single-root
     searches one at a time (parents skipped) on the same GPU and graph."""
@@ -233,13 +266,18 @@ def batch_section(args, torch, np, graphgen, bfsmi):
 
 
 def serve_section(args, torch, np, graphgen, bfsmi):
-    """Open-loop Poisson queries over a pool of resident graphs."""
+    """Open-loop Poisson queries over a pool of resident graphs.  Each result
+    is delivered as int32 levels into a device buffer of the client (one
+    per graph); the client learns of finished queries from the server's
+    completion queue."""
     rng = np.random.default_rng(3000)
     scales = rng.integers(14, 23, size=24)
     graphs = [graphgen.rmat(int(sc), seed=3000 + i) for i, sc in enumerate(scales)]
     graphs += [graphgen.grid(256 * k) for k in range(1, 9)]
+    kinds = ["rmat"] * 24 + ["grid"] * 8
     handles = [bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER) for g in graphs]
     nonzero = [np.nonzero(np.diff(g.off) > 0)[0] for g in graphs]
+    dst = [torch.empty(g.V, dtype=torch.int32, device="cuda") for g in graphs]
     arena = torch.empty(args.serve_arena_gb << 30, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     s = bfsmi.bfs_server_create(arena, max_lanes=64, max_inflight=len(graphs))
@@ -251,16 +289,19 @@ def serve_section(args, torch, np, graphgen, bfsmi):
     gaps = arr.exponential(1.0 / rate, size=n)
     gsel = arr.integers(0, len(graphs), size=n)
     rsel = arr.random(size=n)
-    bufs = {}
     pending = {}
-    lat = []
+    rec = []  # (kind, arrive->done ms, arrive->admit ms, admit->done ms, lanes, levels)
     done_in_window = 0
     t_start = time.monotonic_ns()
     sched = t_start
     i = 0
+    warm_ns = t_start + int(warm * 1e9)
     end_ns = t_start + int((warm + dur) * 1e9)
+    st0 = None
     while True:
         now = time.monotonic_ns()
+        if st0 is None and now >= warm_ns:
+            st0 = bfsmi.bfs_server_get_stats(s)
         while i < n and sched <= now and sched < end_ns:
             gi = int(gsel[i])
             cand = nonzero[gi]
@@ -269,31 +310,49 @@ def serve_section(args, torch, np, graphgen, bfsmi):
             pending[t] = (sched, gi)
             sched += int(gaps[i] * 1e9)
             i += 1
-        for t in list(pending):
-            gi = pending[t][1]
-            buf = bufs.get(gi)
-            if buf is None:
-                buf = bufs[gi] = np.empty(graphs[gi].V, dtype=np.int32)
-            code, tm = bfsmi.bfs_poll(s, t, buf)
-            if code == bfsmi.BFS_OK:
-                arrive, _ = pending.pop(t)
-                if arrive >= t_start + int(warm * 1e9):
-                    lat.append((tm.done_ns - arrive) / 1e6)
-                    if tm.done_ns <= end_ns:
-                        done_in_window += 1
+        for t in bfsmi.bfs_server_completed(s):
+            arrive, gi = pending.pop(t)
+            code, tm = bfsmi.bfs_poll(s, t, dst[gi])
+            if arrive >= warm_ns:
+                rec.append((kinds[gi], (tm.done_ns - arrive) / 1e6, (tm.admit_ns - arrive) / 1e6,
+                            (tm.done_ns - tm.admit_ns) / 1e6, tm.lanes_in_batch, tm.levels))
+                if tm.done_ns <= end_ns:
+                    done_in_window += 1
         if sched >= end_ns and not pending:
             break
         if time.monotonic_ns() > end_ns + int(30e9):
             break
+        time.sleep(0.0001)
+    st1 = bfsmi.bfs_server_get_stats(s)
     bfsmi.bfs_server_destroy(s)
     for h in handles:
         h.close()
-    lat = np.array(lat) if lat else np.zeros(1)
+
+    def pct(xs, q):
+        return round(float(np.percentile(xs, q)), 3) if len(xs) else None
+
+    lat = [r[1] for r in rec]
     res = {"graphs": len(graphs), "offered_qps": rate, "measured_s": dur,
-           "completed": int(len(lat)), "qps": round(done_in_window / dur, 1),
-           "p50_ms": round(float(np.percentile(lat, 50)), 3),
-           "p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "max_ms": round(float(lat.max()), 3), "unfinished": len(pending)}
+           "completed": len(rec), "qps": round(done_in_window / dur, 1),
+           "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+           "max_ms": round(max(lat), 3) if lat else None, "unfinished": len(pending),
+           "delivery": "int32 levels into a client device buffer"}
+    for kind in ("rmat", "grid"):
+        sub = [r for r in rec if r[0] == kind]
+        res[kind] = {"n": len(sub), "p50_ms": pct([r[1] for r in sub], 50),
+                     "p99_ms": pct([r[1] for r in sub], 99),
+                     "wait_p50_ms": pct([r[2] for r in sub], 50),
+                     "run_p50_ms": pct([r[3] for r in sub], 50),
+                     "lanes_mean": round(float(np.mean([r[4] for r in sub])), 2) if sub else None,
+                     "levels_mean": round(float(np.mean([r[5] for r in sub])), 1) if sub else None}
+    if st0 is not None:
+        d = {f: getattr(st1, f) - getattr(st0, f) for f, _ in st1._fields_}
+        res["server"] = {"rounds": int(d["rounds"]), "levels": int(d["levels"]),
+                         "lanes_per_level": round(d["lane_levels"] / max(d["levels"], 1), 2),
+                         "batches": int(d["batches"]),
+                         "device_ms_per_s": round(d["device_ms"] / max(
+                             (time.monotonic_ns() - warm_ns) / 1e9, 1e-9), 1),
+                         "arena_peak_gib": round(st1.arena_peak / 2**30, 2)}
     log("serve: %s" % res)
     return res
 
@@ -310,6 +369,9 @@ def main():
     ap.add_argument("--no-degree-order", action="store_true")
     ap.add_argument("--summary", type=int, default=-1)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--grid-side", type=int, default=4096)
+    ap.add_argument("--grid-roots", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-scale", type=int, default=22)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -348,6 +410,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
         return
     res, g = single_root(args, torch, np, graphgen, bfsmi)
+    grid = None if args.no_grid else grid_section(args, torch, np, graphgen, bfsmi)
     batch = None if args.no_batch else batch_section(args, torch, np, graphgen, bfsmi)
     serve = None if args.no_serve else serve_section(args, torch, np, graphgen, bfsmi)
 
@@ -379,6 +442,8 @@ def main():
     if "cpu_baseline" in res:
         out["cpu_baseline"] = res["cpu_baseline"]
         out["parity_root0"] = res["parity_root0"]
+    if grid is not None:
+        out["grid"] = grid
     if batch is not None:
         out["batch"] = batch
     if serve is not None:

@@ -200,11 +200,40 @@ int bfs_submit(bfs_server *s, int32_t graph_id, int32_t root, uint64_t *ticket);
 
 /*
  * Poll a query.  BFS_PENDING while it runs.  On BFS_OK, if dst_levels is not
- * NULL, copies int32[V] levels of the query's graph into it (host memory),
- * fills *t if not NULL, and retires the ticket.  BFS_ERR_TICKET for unknown
- * or retired tickets.
+ * NULL, writes the int32[V] levels of the query's graph into it (-1 =
+ * unreached), fills *t if not NULL, and retires the ticket.  dst_levels may
+ * be host memory or device memory of the server's device (a device buffer
+ * is filled by a widening kernel and never crosses PCIe).  The call returns
+ * after the copy is complete.  BFS_ERR_TICKET for unknown or retired
+ * tickets.
  */
 int bfs_poll(bfs_server *s, uint64_t ticket, int32_t *dst_levels, bfs_timing *t);
+
+/*
+ * Completion queue: moves up to max_tickets tickets of queries that have
+ * finished (successfully or not) since the last call into tickets[] and
+ * sets *n_out.  Each finished ticket is reported exactly once, so a client
+ * polls only what is done instead of every outstanding ticket.  Reported
+ * tickets stay valid for bfs_poll.
+ */
+int bfs_server_completed(bfs_server *s, uint64_t *tickets, int32_t max_tickets,
+                         int32_t *n_out);
+
+typedef struct bfs_server_stats {
+    uint64_t submitted;    /* queries accepted by bfs_submit                  */
+    uint64_t completed;    /* queries finished, failed ones included          */
+    uint64_t failed;
+    uint64_t rounds;       /* captured level rounds launched                  */
+    uint64_t levels;       /* levels launched, summed over graph batches      */
+    uint64_t lane_levels;  /* sum over launched levels of the live lanes      */
+    uint64_t batches;      /* batch states created (arena allocations)        */
+    uint64_t joins;        /* queries admitted into a lane                    */
+    double   device_ms;    /* device time of all rounds, summed over streams  */
+    uint64_t arena_peak;   /* peak arena bytes in use                         */
+} bfs_server_stats;
+
+/* Counters since bfs_server_create (a consistent snapshot). */
+int bfs_server_get_stats(bfs_server *s, bfs_server_stats *out);
 
 /* Block until every submitted query has finished. */
 int bfs_server_drain(bfs_server *s);

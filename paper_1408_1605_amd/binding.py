@@ -42,8 +42,8 @@ BFS_OPT_VISITED_SUMMARY = 7
 EXPORTS = (
     "bfs_last_error", "bfs_version", "bfs_workspace_bytes", "bfs_graph_create",
     "bfs_graph_destroy", "bfs_set_option", "bfs_get_option", "bfs_run", "bfs_run_batch",
-    "bfs_server_create", "bfs_server_add_graph", "bfs_submit", "bfs_poll", "bfs_server_drain",
-    "bfs_server_destroy",
+    "bfs_server_create", "bfs_server_add_graph", "bfs_submit", "bfs_poll",
+    "bfs_server_completed", "bfs_server_get_stats", "bfs_server_drain", "bfs_server_destroy",
 )
 
 
@@ -71,6 +71,14 @@ class bfs_timing(ctypes.Structure):
     _fields_ = [("submit_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
                 ("done_ns", ctypes.c_int64), ("levels", ctypes.c_int32),
                 ("lanes_in_batch", ctypes.c_int32)]
+
+
+class bfs_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("levels", ctypes.c_uint64), ("lane_levels", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("joins", ctypes.c_uint64),
+                ("device_ms", ctypes.c_double), ("arena_peak", ctypes.c_uint64)]
 
 
 _lib = None
@@ -103,6 +111,9 @@ def load(path: str = LIB_PATH):
         "bfs_server_add_graph": (ctypes.c_int, [vp, vp, ctypes.POINTER(i32)]),
         "bfs_submit": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(ctypes.c_uint64)]),
         "bfs_poll": (ctypes.c_int, [vp, ctypes.c_uint64, vp, ctypes.POINTER(bfs_timing)]),
+        "bfs_server_completed": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint64), i32,
+                                                ctypes.POINTER(i32)]),
+        "bfs_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(bfs_server_stats)]),
         "bfs_server_drain": (ctypes.c_int, [vp]),
         "bfs_server_destroy": (ctypes.c_int, [vp]),
     }
@@ -216,12 +227,35 @@ def bfs_submit(s: int, graph_id: int, root: int) -> int:
 
 
 def bfs_poll(s: int, ticket: int, dst_levels=None):
-    """dst_levels: a host numpy int32[V] array or None.  Returns
-    (status, bfs_timing) with status BFS_OK or BFS_PENDING."""
+    """dst_levels: a host numpy int32[V] array, a device torch int32[V]
+    tensor, or None.  Returns (status, bfs_timing) with status BFS_OK or
+    BFS_PENDING."""
     tm = bfs_timing()
-    ptr = None if dst_levels is None else dst_levels.ctypes.data
+    if dst_levels is None:
+        ptr = None
+    elif hasattr(dst_levels, "data_ptr"):
+        ptr = int(dst_levels.data_ptr())
+    else:
+        ptr = dst_levels.ctypes.data
     code = _check(load().bfs_poll(s, ticket, ptr, ctypes.byref(tm)), allow=(BFS_OK, BFS_PENDING))
     return code, tm
+
+
+_done_buf = (ctypes.c_uint64 * 4096)()
+
+
+def bfs_server_completed(s: int, max_tickets: int = 4096) -> list:
+    """Tickets finished since the last call (each reported once)."""
+    n = ctypes.c_int32(0)
+    m = min(max_tickets, len(_done_buf))
+    _check(load().bfs_server_completed(s, _done_buf, m, ctypes.byref(n)))
+    return list(_done_buf[:n.value])
+
+
+def bfs_server_get_stats(s: int) -> bfs_server_stats:
+    st = bfs_server_stats()
+    _check(load().bfs_server_get_stats(s, ctypes.byref(st)))
+    return st
 
 
 def bfs_server_drain(s: int) -> None:

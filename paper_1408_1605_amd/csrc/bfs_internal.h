@@ -109,6 +109,8 @@ hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, 
                             uint64_t* next, uint32_t* touched, Ctrl* ctrl);
 hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t mask);
 hipError_t launch_fill16(hipStream_t s, int grid, int16_t* p, int64_t n, int16_t val);
+hipError_t launch_widen16(hipStream_t s, int grid, const int16_t* src, int32_t* dst, int64_t n,
+                          int32_t* maxp);
 hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32_t* join,
                            const int32_t* rank, uint64_t* seen, uint64_t* front,
                            int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl);

@@ -196,6 +196,7 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
     __shared__ int64_t s_wave[kWG / 64];
     // +1 word of padding every 8 entries keeps the strided reads conflict-light
     __shared__ int32_t s_deg[kScanChunk + kScanChunk / kScanItems];
+    __shared__ int64_t s_cum[kScanChunk];  // transposes the stores
     if (dev && ctrl->done) return;
     const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
     const int64_t nblk = ((int64_t)qlen + kScanChunk - 1) / kScanChunk;
@@ -223,9 +224,9 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
         for (int j = 0; j < kScanItems; ++j) {
             const int32_t li = threadIdx.x * kScanItems + j;
             const int64_t k = base + li;
+            const int64_t c = start + local[j];
+            s_cum[li] = c;
             if (k < qlen) {
-                const int64_t c = start + local[j];
-                cumul[k] = c;
                 const int32_t d = s_deg[li + li / kScanItems];
                 if (d > 0) {
                     const int64_t t0 = (c + tile - 1) / tile;
@@ -235,7 +236,13 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
                 }
             }
         }
-        __syncthreads();  // s_deg is reused by the next block
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            const int32_t li = j * kWG + threadIdx.x;
+            if (base + li < qlen) cumul[base + li] = s_cum[li];
+        }
+        __syncthreads();  // s_deg and s_cum are reused by the next block
     }
 }
 
@@ -421,32 +428,34 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
         bool ok[EPT];
         int64_t ee[EPT];
         map_tile<EPT>(L, cur, r, cumul, rowstart, uidv, col, uu, vv, ok, ee);
-        // the next tile's staging loads overlap this tile's probes
-        cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
 
         // Early visited test: summary (register / LDS), else a plain load of
         // the bitmap word (a stale word only lets more threads try the atomic).
+        bool known[EPT];
         uint32_t wd[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int32_t v = vv[j];
-            bool known = !ok[j] || v < skip_below;
-            if (!known && summary_words > 0) {
+            known[j] = !ok[j] || v < skip_below;
+            if (!known[j] && summary_words > 0) {
                 const uint32_t b = (uint32_t)v >> shift;
-                known = (s_sum[b >> 5] >> (b & 31)) & 1u;
+                known[j] = (s_sum[b >> 5] >> (b & 31)) & 1u;
             }
-            wd[j] = known ? 0xffffffffu : vis[v >> 5];
+            if (!known[j]) wd[j] = vis[v >> 5];
+        }
+        // the next tile's staging loads overlap this tile's probes and claims
+        cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
+        // claims: issue every atomic before using any result
+        bool need[EPT];
+        uint32_t old[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            need[j] = !known[j] && !(wd[j] & (1u << (vv[j] & 31)));
+            if (need[j]) old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
         }
         bool win[EPT];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            win[j] = false;
-            const uint32_t m = 1u << (vv[j] & 31);
-            if (ok[j] && !(wd[j] & m)) {
-                const uint32_t old = atomicOr(vis + (vv[j] >> 5), m);
-                win[j] = !(old & m);
-            }
-        }
+        for (int j = 0; j < EPT; ++j) win[j] = need[j] && !(old[j] & (1u << (vv[j] & 31)));
         int32_t vo[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) vo[j] = (win[j] && orig) ? orig[vv[j]] : vv[j];

@@ -385,6 +385,26 @@ __global__ __launch_bounds__(kWG) void k_fill16(int16_t* __restrict__ p, int64_t
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) p[i] = val;
 }
 
+// dst[i] = src[i] widened to int32, and *maxp = max(*maxp, max src[i]):
+// delivery of a serving result into a device buffer of the caller.
+__global__ __launch_bounds__(kWG) void k_widen16(const int16_t* __restrict__ src,
+                                                 int32_t* __restrict__ dst, int64_t n,
+                                                 int32_t* __restrict__ maxp)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    int32_t m = -1;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) {
+        const int32_t x = src[i];
+        dst[i] = x;
+        m = x > m ? x : m;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        const int32_t o = __shfl_xor(m, d, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m >= 0) atomicMax(maxp, m);
+}
+
 // Lane join_lane[i] starts a search from join_root[i] (caller id).  Its
 // root gets depth 0; its first expansion is the next level, so
 // lane_start = level - 1.  Roots not yet in the union frontier are appended.
@@ -440,6 +460,13 @@ hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, 
 hipError_t launch_fill16(hipStream_t s, int grid, int16_t* p, int64_t n, int16_t val)
 {
     hipLaunchKernelGGL(k_fill16, dim3(grid), dim3(kWG), 0, s, p, n, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen16(hipStream_t s, int grid, const int16_t* src, int32_t* dst, int64_t n,
+                          int32_t* maxp)
+{
+    hipLaunchKernelGGL(k_widen16, dim3(grid), dim3(kWG), 0, s, src, dst, n, maxp);
     return hipGetLastError();
 }
 

@@ -11,6 +11,18 @@
 // arena; a graph's batch starts only when its state fits the free arena
 // (admission by HBM budget), and a query joins only when its result fits.
 // Different graphs' batches run concurrently on their streams.
+//
+// Admission into a running batch follows the graph's depth.  On a
+// small-world graph every search touches most edges at its one or two
+// widest levels; lanes that start together share those levels in one
+// expansion, while a lane that joins later pays them again on its own.  So
+// on such a graph new queries join only at the start of a batch (waves).
+// On a deep graph (lanes live for many cheap levels) and on a small graph
+// a query joins at the next level boundary (continuous batching).  The
+// depth is learnt per graph from the lifetimes of retired lanes.
+//
+// The worker takes the server lock only to move queries and arena blocks;
+// its HIP calls run unlocked, so submit/poll never wait behind a launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,6 +69,8 @@ public:
                 free_.erase(it);
                 if (len > bytes) free_[off + bytes] = len - bytes;
                 used_[off] = bytes;
+                in_use_ += bytes;
+                peak_ = std::max(peak_, in_use_);
                 return base_ + off;
             }
         }
@@ -70,6 +84,7 @@ public:
         if (u == used_.end()) return;
         size_t len = u->second;
         used_.erase(u);
+        in_use_ -= len;
         size_t start = off;
         auto nx = free_.lower_bound(off);
         if (nx != free_.end() && nx->first == off + len) {
@@ -88,8 +103,10 @@ public:
         free_[start] = len;
     }
     size_t size() const { return size_; }
+    size_t peak() const { return peak_; }
 
 private:
+    size_t in_use_ = 0, peak_ = 0;
     char* base_ = nullptr;
     size_t size_ = 0;
     std::map<size_t, size_t> free_;
@@ -101,6 +118,7 @@ struct SrvQuery {
     int32_t root = 0;
     int64_t submit_ns = 0, admit_ns = 0, done_ns = 0;
     int32_t lanes = 0;
+    int32_t levels = 0;         // depth + 1, from the lane's lifetime
     int16_t* result = nullptr;  // arena, int16[V]
     int state = 0;              // 0 pending, 1 running, 2 done, 3 failed
     int err = 0;
@@ -123,7 +141,7 @@ struct SrvBatch {
     int32_t* lane_start = nullptr; // device int32[64]
     int32_t* join = nullptr;       // device int32[128] (root, lane) pairs
     uint64_t lane_ticket[64] = {};
-    int64_t lane_age[64] = {};     // levels run since the lane joined
+    int64_t lane_age[64] = {};     // levels launched since the lane joined
     uint64_t active = 0;
     int parity = 0;                // stays 0: every replay runs an even number of levels
     bool in_flight = false;
@@ -133,17 +151,33 @@ struct SrvBatch {
 
 constexpr int kRoundLevels[3] = {2, 8, 32};
 constexpr int64_t kIdleKeepNs = 100 * 1000 * 1000;  // idle batches kept 100 ms
+constexpr double kDeepLife = 48.0;                  // lanes living longer: continuous joins
+constexpr int32_t kSmallV = 1 << 16;                // graphs this small: continuous joins
 
 struct SrvGraph {
     bfs_graph* g = nullptr;
     size_t state_bytes = 0;
     std::deque<uint64_t> pending;
-    SrvBatch* batch = nullptr;
+    SrvBatch* batch = nullptr;     // worker thread only
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev0 = nullptr, ev = nullptr;  // round start / end (timing events)
     Ctrl* h_ctrl = nullptr;        // pinned
     int16_t** h_lane_out = nullptr;  // pinned staging for the lane table
     int32_t* h_join = nullptr;     // pinned staging for joins
+    double life = 0.0;             // smoothed lane lifetime in levels
+    int64_t life_n = 0;
+};
+
+// What one worker step launches for a graph, decided under the lock and
+// carried out without it.
+struct StepPlan {
+    bool fresh = false;      // batch created: reset its state, capture its rounds
+    bool reset = false;      // device error or depth overflow: reset all lanes
+    uint64_t clear = 0;      // retired lanes whose seen bits are cleared
+    int n_join = 0;          // staged in h_join / h_lane_out
+    int16_t* fill[64] = {};  // result buffers of the joining lanes
+    int round = -1;          // round to replay, -1 none
+    bool release = false;    // idle too long: give the batch's memory back
 };
 
 static size_t batch_state_bytes(const bfs_graph* g)
@@ -173,15 +207,33 @@ struct bfs_server {
     std::mutex mu;
     std::condition_variable cv;       // wakes the worker
     std::condition_variable idle_cv;  // signals drain()
-    std::vector<SrvGraph> graphs;
+    std::deque<SrvGraph> graphs;      // deque: references stay valid on growth
     std::unordered_map<uint64_t, SrvQuery> queries;
+    std::vector<uint64_t> done_list;  // finished, not yet reported by bfs_server_completed
+    std::atomic<int64_t> n_done_list{0};
     uint64_t next_ticket = 1;
     int64_t outstanding = 0;
     std::atomic<bool> stop{false};
     int worker_err = 0;
+    bfs_server_stats stats{};
+    // result delivery (bfs_poll)
+    std::mutex poll_mu;
+    hipStream_t poll_stream = nullptr;
+    int32_t* d_max = nullptr;         // arena, one int32
+    int32_t* h_max = nullptr;         // pinned
+    int16_t* h_stage = nullptr;       // pinned, int16[stage_elems]
+    size_t stage_elems = 0;
     std::thread worker;
     void run();
-    bool step_graph(SrvGraph& G, int gid);
+    bool step_graph(SrvGraph& G);
+    bool plan_step(SrvGraph& G, bool round_done, bool round_err, StepPlan& P);
+    void execute(SrvGraph& G, const StepPlan& P);
+    void set_err(int e)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!worker_err) worker_err = e;
+        idle_cv.notify_all();
+    }
 };
 
 namespace {
@@ -223,23 +275,51 @@ int capture_rounds(const bfs_graph* g, SrvBatch* B, hipStream_t s)
     return BFS_OK;
 }
 
-void free_batch(Arena& arena, SrvGraph& G)
+// Device side of releasing a batch (worker thread; the stream is idle or
+// about to be): wait for the stream and destroy the captured rounds.
+void drop_batch_device(SrvGraph& G)
 {
     SrvBatch* B = G.batch;
-    if (!B) return;
     (void)hipStreamSynchronize(G.stream);
     for (auto& r : B->round)
         if (r) (void)hipGraphExecDestroy(r);
-    arena.release(B->mem);
-    delete B;
-    G.batch = nullptr;
+}
+
+SrvBatch* carve_batch(char* mem, const bfs_graph* g)
+{
+    SrvBatch* B = new SrvBatch();
+    B->mem = mem;
+    char* p = mem;
+    auto take = [&](size_t bytes) {
+        char* at = p;
+        p += align256(bytes);
+        return at;
+    };
+    const size_t V = (size_t)g->V;
+    B->seen = (uint64_t*)take(V * 8);
+    B->front = (uint64_t*)take(V * 8);
+    B->next = (uint64_t*)take(V * 8);
+    B->touched = (uint32_t*)take((V + 31) / 32 * 4);
+    B->q[0] = (int32_t*)take(V * 4);
+    B->q[1] = (int32_t*)take(V * 4);
+    B->deg = (int32_t*)take(V * 4);
+    B->rowstart = (int64_t*)take(V * 8);
+    B->suid = (int32_t*)take(V * 4);
+    B->cumul = (int64_t*)take((V + 1) * 8);
+    B->bsum = (int64_t*)take(((V + kScanChunk - 1) / kScanChunk + 1) * 8);
+    B->tile_k = (int32_t*)take((size_t)((g->nnz + kMinTile - 1) / kMinTile + 2) * 4);
+    B->ctrl = (Ctrl*)take(sizeof(Ctrl));
+    B->lane_out = (int16_t**)take(64 * 8);
+    B->lane_start = (int32_t*)take(64 * 4);
+    B->join = (int32_t*)take(128 * 4);
+    return B;
 }
 
 }  // namespace
 
-// One scheduling step for graph G; returns true when it launched work.
-// Called by the worker with mu held; device calls are short and async.
-bool bfs_server::step_graph(SrvGraph& G, int gid)
+// Decide one step for graph G (server lock held).  Returns false when the
+// graph has nothing to launch or to release.
+bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPlan& P)
 {
     const bfs_graph* g = G.g;
     SrvBatch* B = G.batch;
@@ -252,148 +332,205 @@ bool bfs_server::step_graph(SrvGraph& G, int gid)
         if (!mem) {
             // release idle batches of other graphs, then retry once
             for (auto& o : graphs)
-                if (o.batch && o.batch->idle_since != 0) free_batch(arena, o);
+                if (o.batch && o.batch->idle_since != 0 && !o.batch->in_flight) {
+                    drop_batch_device(o);
+                    arena.release(o.batch->mem);
+                    delete o.batch;
+                    o.batch = nullptr;
+                }
             mem = arena.alloc(G.state_bytes);
         }
         if (!mem) return false;  // over budget: wait for memory to free up
-        B = new SrvBatch();
-        B->mem = mem;
-        char* p = mem;
-        auto take = [&](size_t bytes) {
-            char* at = p;
-            p += align256(bytes);
-            return at;
-        };
-        const size_t V = (size_t)g->V;
-        B->seen = (uint64_t*)take(V * 8);
-        B->front = (uint64_t*)take(V * 8);
-        B->next = (uint64_t*)take(V * 8);
-        B->touched = (uint32_t*)take((V + 31) / 32 * 4);
-        B->q[0] = (int32_t*)take(V * 4);
-        B->q[1] = (int32_t*)take(V * 4);
-        B->deg = (int32_t*)take(V * 4);
-        B->rowstart = (int64_t*)take(V * 8);
-        B->suid = (int32_t*)take(V * 4);
-        B->cumul = (int64_t*)take((V + 1) * 8);
-        B->bsum = (int64_t*)take(((V + kScanChunk - 1) / kScanChunk + 1) * 8);
-        B->tile_k = (int32_t*)take((size_t)((g->nnz + kMinTile - 1) / kMinTile + 2) * 4);
-        B->ctrl = (Ctrl*)take(sizeof(Ctrl));
-        B->lane_out = (int16_t**)take(64 * 8);
-        B->lane_start = (int32_t*)take(64 * 4);
-        B->join = (int32_t*)take(128 * 4);
+        B = carve_batch(mem, g);
         G.batch = B;
-        if (launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->touched, B->ctrl) !=
-            hipSuccess)
-            worker_err = BFS_ERR_HIP;
-        if (capture_rounds(g, B, G.stream) != BFS_OK) worker_err = BFS_ERR_HIP;
+        P.fresh = true;
+        ++stats.batches;
     }
-    if (B->in_flight) {
-        if (hipEventQuery(G.ev) != hipSuccess) return false;
-        B->in_flight = false;
+    if (round_done) {
         const Ctrl& c = *G.h_ctrl;
+        const bool bad = round_err || c.err || c.overflow;
+        const uint64_t retired = bad ? B->active : (B->active & ~c.last_alive);
         const int64_t t = now_ns();
-        uint64_t retired = B->active & ~c.last_alive;
-        if (c.err || c.overflow) retired = B->active;  // fail every running lane
         for (int b = 0; b < 64; ++b) {
             if (!((retired >> b) & 1ull)) continue;
             auto it = queries.find(B->lane_ticket[b]);
             if (it != queries.end()) {
-                it->second.done_ns = t;
-                it->second.state = (c.err || c.overflow) ? 3 : 2;
-                it->second.err = c.err ? BFS_ERR_HIP : (c.overflow ? BFS_ERR_DEPTH : 0);
+                SrvQuery& q = it->second;
+                q.done_ns = t;
+                q.state = bad ? 3 : 2;
+                q.err = bad ? (c.overflow && !c.err && !round_err ? BFS_ERR_DEPTH : BFS_ERR_HIP) : 0;
+                done_list.push_back(it->first);
+                ++stats.completed;
+                stats.failed += bad;
+            }
+            if (!bad) {
+                const double life = (double)B->lane_age[b];
+                G.life = G.life_n ? 0.75 * G.life + 0.25 * life : life;
+                ++G.life_n;
             }
             --outstanding;
         }
+        n_done_list.store((int64_t)done_list.size());
         B->active &= ~retired;
         if (retired) {
-            if (c.err || c.overflow) {
-                (void)launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next, B->touched, B->ctrl);
-            } else {
-                (void)launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->seen, retired);
-            }
+            if (bad) P.reset = true;
+            else P.clear = retired;
             idle_cv.notify_all();
         }
     }
     // boundary: fill free lanes from the queue (FIFO, while results fit)
-    int n_join = 0;
+    int64_t oldest = 0;
+    for (int b = 0; b < 64; ++b)
+        if ((B->active >> b) & 1ull) oldest = std::max(oldest, B->lane_age[b]);
+    const bool deep = G.life_n > 0 && G.life > kDeepLife;
+    const bool continuous = deep || g->V <= kSmallV;
     const uint64_t lane_cap = cfg.max_lanes >= 64 ? ~0ull : ((1ull << cfg.max_lanes) - 1);
-    while (!G.pending.empty() && (~B->active & lane_cap)) {
-        const uint64_t ticket = G.pending.front();
-        SrvQuery& q = queries[ticket];
-        char* res = arena.alloc((size_t)g->V * 2);
-        if (!res) break;
-        G.pending.pop_front();
-        const int b = __builtin_ctzll(~B->active & lane_cap);
-        B->active |= 1ull << b;
-        B->lane_ticket[b] = ticket;
-        B->lane_age[b] = 0;
-        q.result = reinterpret_cast<int16_t*>(res);
-        q.state = 1;
-        q.admit_ns = now_ns();
-        G.h_join[2 * n_join] = q.root;
-        G.h_join[2 * n_join + 1] = b;
-        G.h_lane_out[b] = q.result;
-        (void)launch_fill16(G.stream, g->num_cus * 2, q.result, g->V, (int16_t)-1);
-        ++n_join;
-    }
-    if (n_join) {
-        const int lanes = __builtin_popcountll(B->active);
-        for (int i = 0; i < n_join; ++i) queries[B->lane_ticket[G.h_join[2 * i + 1]]].lanes = lanes;
-        if (hipMemcpyAsync(B->lane_out, G.h_lane_out, 64 * sizeof(int16_t*), hipMemcpyHostToDevice,
-                           G.stream) != hipSuccess ||
-            hipMemcpyAsync(B->join, G.h_join, (size_t)n_join * 2 * sizeof(int32_t),
-                           hipMemcpyHostToDevice, G.stream) != hipSuccess ||
-            launch_srv_join(G.stream, g->V, n_join, B->join, g->rank, B->seen, B->front,
-                            B->lane_out, B->lane_start, B->q[B->parity], B->ctrl) != hipSuccess)
-            worker_err = BFS_ERR_HIP;
+    if (continuous || oldest == 0) {
+        while (!G.pending.empty() && (~B->active & lane_cap)) {
+            const uint64_t ticket = G.pending.front();
+            SrvQuery& q = queries[ticket];
+            char* res = arena.alloc((size_t)g->V * 2);
+            if (!res) break;
+            G.pending.pop_front();
+            const int b = __builtin_ctzll(~B->active & lane_cap);
+            B->active |= 1ull << b;
+            B->lane_ticket[b] = ticket;
+            B->lane_age[b] = 0;
+            q.result = reinterpret_cast<int16_t*>(res);
+            q.state = 1;
+            q.admit_ns = now_ns();
+            G.h_join[2 * P.n_join] = q.root;
+            G.h_join[2 * P.n_join + 1] = b;
+            G.h_lane_out[b] = q.result;
+            P.fill[P.n_join] = q.result;
+            ++P.n_join;
+        }
+        if (P.n_join) {
+            const int lanes = __builtin_popcountll(B->active);
+            for (int i = 0; i < P.n_join; ++i)
+                queries[B->lane_ticket[G.h_join[2 * i + 1]]].lanes = lanes;
+            stats.joins += P.n_join;
+        }
     }
     if (!B->active) {
         // nothing running: keep the batch a little for the next query, then
         // release its arena memory
         const int64_t t = now_ns();
         if (B->idle_since == 0) B->idle_since = t;
-        if (t - B->idle_since > kIdleKeepNs) free_batch(arena, G);
-        return false;
+        if (t - B->idle_since > kIdleKeepNs) P.release = true;
+        return P.fresh || P.reset || P.clear || P.release;
     }
     B->idle_since = 0;
-    // levels per replay: 2 while every lane is young, more for deep searches
-    int64_t oldest = 0;
-    for (int b = 0; b < 64; ++b)
-        if ((B->active >> b) & 1ull) oldest = std::max(oldest, B->lane_age[b]);
-    const int ri = oldest < 32 ? 0 : (oldest < 256 ? 1 : 2);
+    // levels per replay: waves run 8 (most small-world searches end within
+    // one replay; levels after every lane has ended exit at once); deep
+    // graphs start with 2 and lengthen as their oldest lane ages
+    const int ri = !deep ? 1 : (oldest < 32 ? 0 : (oldest < 256 ? 1 : 2));
     const int K = kRoundLevels[ri];
-    if (!B->round[ri] || hipGraphLaunch(B->round[ri], G.stream) != hipSuccess) worker_err = BFS_ERR_HIP;
+    P.round = ri;
+    ++stats.rounds;
+    stats.levels += (uint64_t)K;
+    stats.lane_levels += (uint64_t)K * (uint64_t)__builtin_popcountll(B->active);
     for (int b = 0; b < 64; ++b)
         if ((B->active >> b) & 1ull) B->lane_age[b] += K;
-    if (hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, G.stream) !=
-            hipSuccess ||
-        hipEventRecord(G.ev, G.stream) != hipSuccess)
-        worker_err = BFS_ERR_HIP;
-    B->in_flight = true;
-    (void)gid;
     return true;
+}
+
+// Carry out a plan (no lock held; only the worker touches G.batch).
+void bfs_server::execute(SrvGraph& G, const StepPlan& P)
+{
+    const bfs_graph* g = G.g;
+    SrvBatch* B = G.batch;
+    bool bad = false;
+    if (P.fresh) {
+        bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next,
+                                B->touched, B->ctrl) != hipSuccess;
+        bad |= capture_rounds(g, B, G.stream) != BFS_OK;
+    }
+    if (P.reset)
+        bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next,
+                                B->touched, B->ctrl) != hipSuccess;
+    else if (P.clear)
+        bad |= launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->seen, P.clear) != hipSuccess;
+    for (int i = 0; i < P.n_join; ++i)
+        bad |= launch_fill16(G.stream, g->num_cus * 2, P.fill[i], g->V, (int16_t)-1) != hipSuccess;
+    if (P.n_join) {
+        bad |= hipMemcpyAsync(B->lane_out, G.h_lane_out, 64 * sizeof(int16_t*),
+                              hipMemcpyHostToDevice, G.stream) != hipSuccess;
+        bad |= hipMemcpyAsync(B->join, G.h_join, (size_t)P.n_join * 2 * sizeof(int32_t),
+                              hipMemcpyHostToDevice, G.stream) != hipSuccess;
+        bad |= launch_srv_join(G.stream, g->V, P.n_join, B->join, g->rank, B->seen, B->front,
+                               B->lane_out, B->lane_start, B->q[B->parity], B->ctrl) != hipSuccess;
+    }
+    if (P.release) {
+        drop_batch_device(G);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            arena.release(B->mem);
+        }
+        delete B;
+        G.batch = nullptr;
+    } else if (P.round >= 0) {
+        bad |= hipEventRecord(G.ev0, G.stream) != hipSuccess;
+        bad |= !B->round[P.round] || hipGraphLaunch(B->round[P.round], G.stream) != hipSuccess;
+        bad |= hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, G.stream) !=
+               hipSuccess;
+        bad |= hipEventRecord(G.ev, G.stream) != hipSuccess;
+        B->in_flight = true;
+    }
+    if (bad) set_err(BFS_ERR_HIP);
+}
+
+// One scheduling step for graph G; returns true when it launched work.
+bool bfs_server::step_graph(SrvGraph& G)
+{
+    SrvBatch* B = G.batch;
+    bool round_done = false, round_err = false;
+    double round_ms = 0.0;
+    if (B && B->in_flight) {
+        const hipError_t q = hipEventQuery(G.ev);
+        if (q == hipErrorNotReady) return false;
+        if (q == hipSuccess) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, G.ev0, G.ev) == hipSuccess) round_ms = ms;
+        } else {
+            round_err = true;
+            set_err(BFS_ERR_HIP);
+        }
+        B->in_flight = false;
+        round_done = true;
+    }
+    StepPlan P;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stats.device_ms += round_ms;
+        if (!plan_step(G, round_done, round_err, P)) return false;
+    }
+    execute(G, P);
+    return P.round >= 0;
 }
 
 void bfs_server::run()
 {
     (void)hipSetDevice(device);
-    std::unique_lock<std::mutex> lk(mu);
+    std::vector<SrvGraph*> gl;
     while (!stop.load()) {
-        bool busy = false;
-        bool waiting = false;
-        for (size_t i = 0; i < graphs.size(); ++i) {
-            busy |= step_graph(graphs[i], (int)i);
-            waiting |= graphs[i].batch != nullptr || !graphs[i].pending.empty();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            gl.clear();
+            for (auto& G : graphs) gl.push_back(&G);
         }
-        if (!busy) {
-            // poll in-flight rounds at a fine grain; sleep when idle
-            if (waiting) {
-                lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-                lk.lock();
-            } else {
-                cv.wait_for(lk, std::chrono::milliseconds(5));
-            }
+        bool busy = false;
+        for (SrvGraph* G : gl) busy |= step_graph(*G);
+        if (busy) continue;
+        std::unique_lock<std::mutex> lk(mu);
+        bool waiting = false;
+        for (const auto& G : graphs) waiting |= G.batch != nullptr || !G.pending.empty();
+        if (waiting) {
+            // poll in-flight rounds at a fine grain
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        } else {
+            cv.wait_for(lk, std::chrono::milliseconds(5));
         }
     }
 }
@@ -405,7 +542,7 @@ int bfs_server_create(bfs_server** out, void* d_arena, size_t arena_bytes,
 {
     if (!out) return fail(BFS_ERR_INVALID, "server out-pointer is NULL");
     *out = nullptr;
-    if (!d_arena || arena_bytes < 256) return fail(BFS_ERR_INVALID, "arena is NULL or too small");
+    if (!d_arena || arena_bytes < 4096) return fail(BFS_ERR_INVALID, "arena is NULL or too small");
     if ((uintptr_t)d_arena % 256) return fail(BFS_ERR_INVALID, "arena not 256-byte aligned");
     bfs_server_config c{64, 8, 0};
     if (cfg) {
@@ -415,17 +552,30 @@ int bfs_server_create(bfs_server** out, void* d_arena, size_t arena_bytes,
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BFS_ERR_NO_DEVICE, "no HIP device");
-    bfs_server* s = new (std::nothrow) bfs_server();
-    if (!s) return fail(BFS_ERR_INVALID, "out of host memory");
-    s->cfg = c;
-    s->arena.init(static_cast<char*>(d_arena), arena_bytes);
     int dev = 0;
     (void)hipGetDevice(&dev);
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, d_arena) == hipSuccess && attr.type == hipMemoryTypeDevice)
         dev = attr.device;
     (void)hipGetLastError();
+    bfs_server* s = new (std::nothrow) bfs_server();
+    if (!s) return fail(BFS_ERR_INVALID, "out of host memory");
+    s->cfg = c;
     s->device = dev;
+    // the first 256 bytes of the arena hold the delivery kernel's maximum
+    s->d_max = static_cast<int32_t*>(d_arena);
+    s->arena.init(static_cast<char*>(d_arena) + 256, arena_bytes - 256);
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(dev);
+    hipError_t e = hipStreamCreateWithFlags(&s->poll_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_max, 256, hipHostMallocDefault);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (s->poll_stream) (void)hipStreamDestroy(s->poll_stream);
+        delete s;
+        return hip_fail(e, "server resources");
+    }
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return ok();
@@ -444,14 +594,30 @@ int bfs_server_add_graph(bfs_server* s, bfs_graph* g, int32_t* graph_id)
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
     hipError_t e = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&G.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&G.ev0);
+    if (e == hipSuccess) e = hipEventCreate(&G.ev);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&G.h_ctrl, sizeof(Ctrl) + 64 * sizeof(int16_t*) + 128 * sizeof(int32_t),
                           hipHostMallocDefault);
+    {
+        // pinned staging for host-side delivery, sized for the largest graph
+        std::lock_guard<std::mutex> pl(s->poll_mu);
+        if (e == hipSuccess && (size_t)g->V > s->stage_elems) {
+            int16_t* st = nullptr;
+            e = hipHostMalloc((void**)&st, (size_t)g->V * 2, hipHostMallocDefault);
+            if (e == hipSuccess) {
+                if (s->h_stage) (void)hipHostFree(s->h_stage);
+                s->h_stage = st;
+                s->stage_elems = (size_t)g->V;
+            }
+        }
+    }
     (void)hipSetDevice(prev);
     if (e != hipSuccess) {
         if (G.stream) (void)hipStreamDestroy(G.stream);
+        if (G.ev0) (void)hipEventDestroy(G.ev0);
         if (G.ev) (void)hipEventDestroy(G.ev);
+        if (G.h_ctrl) (void)hipHostFree(G.h_ctrl);
         return hip_fail(e, "server graph resources");
     }
     G.h_lane_out = reinterpret_cast<int16_t**>(G.h_ctrl + 1);
@@ -480,6 +646,7 @@ int bfs_submit(bfs_server* s, int32_t graph_id, int32_t root, uint64_t* ticket)
     s->queries.emplace(t, q);
     G.pending.push_back(t);
     ++s->outstanding;
+    ++s->stats.submitted;
     *ticket = t;
     s->cv.notify_one();
     return ok();
@@ -491,44 +658,92 @@ int bfs_poll(bfs_server* s, uint64_t ticket, int32_t* dst_levels, bfs_timing* tm
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->queries.find(ticket);
     if (it == s->queries.end()) return fail(BFS_ERR_TICKET, "unknown ticket %llu", (unsigned long long)ticket);
-    SrvQuery q = it->second;
+    const SrvQuery q = it->second;
     if (q.state < 2) return BFS_PENDING;
     const int32_t V = s->graphs[q.graph].g->V;
+    lk.unlock();
     int rc = BFS_OK;
+    int32_t levels = 0;
     if (q.state == 3) {
         rc = fail(q.err ? q.err : BFS_ERR_HIP, "query failed on the device");
     } else if (dst_levels) {
-        lk.unlock();
-        std::vector<int16_t> tmp((size_t)V);
+        std::lock_guard<std::mutex> pl(s->poll_mu);
         int prev = 0;
         (void)hipGetDevice(&prev);
         (void)hipSetDevice(s->device);
-        hipError_t e = hipMemcpy(tmp.data(), q.result, (size_t)V * 2, hipMemcpyDeviceToHost);
-        (void)hipSetDevice(prev);
-        if (e != hipSuccess) return hip_fail(e, "result copy");
-        int32_t lv = -1;
-        for (int32_t v = 0; v < V; ++v) {
-            dst_levels[v] = tmp[(size_t)v];
-            lv = std::max<int32_t>(lv, tmp[(size_t)v]);
+        hipPointerAttribute_t attr;
+        const bool on_device = hipPointerGetAttributes(&attr, dst_levels) == hipSuccess &&
+                               attr.type == hipMemoryTypeDevice && attr.device == s->device;
+        (void)hipGetLastError();
+        hipError_t e;
+        if (on_device) {
+            e = hipMemsetAsync(s->d_max, 0xff, sizeof(int32_t), s->poll_stream);
+            if (e == hipSuccess) {
+                const int grid = (int)std::min<int64_t>(((int64_t)V + 4095) / 4096, 1024);
+                e = launch_widen16(s->poll_stream, std::max(grid, 1), q.result, dst_levels, V, s->d_max);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s->h_max, s->d_max, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   s->poll_stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->poll_stream);
+            levels = *s->h_max + 1;
+        } else {
+            e = hipMemcpyAsync(s->h_stage, q.result, (size_t)V * 2, hipMemcpyDeviceToHost,
+                               s->poll_stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->poll_stream);
+            int32_t lv = -1;
+            if (e == hipSuccess) {
+                const int16_t* src = s->h_stage;
+                for (int32_t v = 0; v < V; ++v) {
+                    const int32_t x = src[v];
+                    dst_levels[v] = x;
+                    lv = x > lv ? x : lv;
+                }
+            }
+            levels = lv + 1;
         }
-        q.lanes = q.lanes ? q.lanes : 1;
-        lk.lock();
-        it = s->queries.find(ticket);
-        if (tm) tm->levels = lv + 1;
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) return hip_fail(e, "result delivery");
     }
     if (tm) {
         tm->submit_ns = q.submit_ns;
         tm->admit_ns = q.admit_ns;
         tm->done_ns = q.done_ns;
-        tm->lanes_in_batch = q.lanes;
-        if (!dst_levels || q.state == 3) tm->levels = 0;
+        tm->lanes_in_batch = q.lanes ? q.lanes : 1;
+        tm->levels = (dst_levels && q.state == 2) ? levels : 0;
     }
+    lk.lock();
+    it = s->queries.find(ticket);
     if (it != s->queries.end()) {
         s->arena.release(reinterpret_cast<char*>(it->second.result));
         s->queries.erase(it);
     }
     s->cv.notify_one();
     return rc == BFS_OK ? ok() : rc;
+}
+
+int bfs_server_completed(bfs_server* s, uint64_t* tickets, int32_t max_tickets, int32_t* n_out)
+{
+    if (!s || !n_out || (max_tickets > 0 && !tickets) || max_tickets < 0)
+        return fail(BFS_ERR_INVALID, "NULL argument or negative max_tickets");
+    *n_out = 0;
+    if (s->n_done_list.load() == 0 || max_tickets == 0) return ok();
+    std::lock_guard<std::mutex> lk(s->mu);
+    const size_t n = std::min<size_t>((size_t)max_tickets, s->done_list.size());
+    std::copy(s->done_list.begin(), s->done_list.begin() + n, tickets);
+    s->done_list.erase(s->done_list.begin(), s->done_list.begin() + n);
+    s->n_done_list.store((int64_t)s->done_list.size());
+    *n_out = (int32_t)n;
+    return ok();
+}
+
+int bfs_server_get_stats(bfs_server* s, bfs_server_stats* out)
+{
+    if (!s || !out) return fail(BFS_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->arena_peak = (uint64_t)s->arena.peak();
+    return ok();
 }
 
 int bfs_server_drain(bfs_server* s)
@@ -551,11 +766,20 @@ int bfs_server_destroy(bfs_server* s)
     (void)hipSetDevice(s->device);
     for (auto& G : s->graphs) {
         if (G.stream) (void)hipStreamSynchronize(G.stream);
-        free_batch(s->arena, G);
+        if (G.batch) {
+            drop_batch_device(G);
+            s->arena.release(G.batch->mem);
+            delete G.batch;
+            G.batch = nullptr;
+        }
         if (G.stream) (void)hipStreamDestroy(G.stream);
+        if (G.ev0) (void)hipEventDestroy(G.ev0);
         if (G.ev) (void)hipEventDestroy(G.ev);
         if (G.h_ctrl) (void)hipHostFree(G.h_ctrl);
     }
+    if (s->poll_stream) (void)hipStreamDestroy(s->poll_stream);
+    if (s->h_max) (void)hipHostFree(s->h_max);
+    if (s->h_stage) (void)hipHostFree(s->h_stage);
     (void)hipSetDevice(prev);
     delete s;
     return ok();

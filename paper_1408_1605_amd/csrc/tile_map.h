@@ -45,7 +45,10 @@ struct StageRegs {
     int32_t uid[TileLds<EPT>::PER];
 };
 
-// Issue the loads of tile `tile`'s staging entries (tile < 0: nothing).
+// Issue the loads of tile `tile`'s staging entries (tile >= ntiles: a
+// harmless in-range load, marked invalid).  The loads are unconditional,
+// with indices clamped into [k_lo, k_hi], so the compiler can count them
+// and wait for earlier loads without waiting for these.
 template <int EPT>
 __device__ __forceinline__ StageRegs<EPT> fetch_stage(int32_t tile, int32_t ntiles,
                                                       const int64_t* __restrict__ cumul,
@@ -54,24 +57,18 @@ __device__ __forceinline__ StageRegs<EPT> fetch_stage(int32_t tile, int32_t ntil
                                                       const int32_t* __restrict__ tile_k)
 {
     StageRegs<EPT> R;
-    R.tile = tile < ntiles ? tile : -1;
-    R.k_lo = 0;
-    R.k_hi = -1;
-    if (R.tile < 0) return R;
-    R.k_lo = tile_k[tile];
-    R.k_hi = tile_k[tile + 1];
-    const int32_t n_k = R.k_hi - R.k_lo + 1;
-    if (n_k <= TileLds<EPT>::CAP + 1) {
+    const bool valid = tile < ntiles;
+    R.tile = valid ? tile : -1;
+    const int32_t t = valid ? tile : 0;
+    R.k_lo = valid ? tile_k[t] : 0;
+    R.k_hi = valid ? tile_k[t + 1] : 0;
 #pragma unroll
-        for (int m = 0; m < TileLds<EPT>::PER; ++m) {
-            const int32_t i = threadIdx.x + m * kWG;
-            if (i < n_k) {
-                const int32_t k = R.k_lo + i;
-                R.cum[m] = cumul[k];
-                R.rs[m] = rowstart[k];
-                R.uid[m] = uidv[k];
-            }
-        }
+    for (int m = 0; m < TileLds<EPT>::PER; ++m) {
+        int32_t k = R.k_lo + (int32_t)threadIdx.x + m * kWG;
+        k = k < R.k_hi ? k : R.k_hi;
+        R.cum[m] = cumul[k];
+        R.rs[m] = rowstart[k];
+        R.uid[m] = uidv[k];
     }
     return R;
 }
@@ -128,18 +125,16 @@ __device__ __forceinline__ void map_tile(TileLds<EPT>& L, const StageRegs<EPT>& 
             }
         }
         __syncthreads();
+        // unconditional loads: slots past the tile's last edge re-read it
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const int32_t sl = threadIdx.x + j * kWG;
-            ok[j] = sl < n_e;
-            uid[j] = 0;
-            col_val[j] = 0;
-            eidx[j] = e0 + sl;
-            if (ok[j]) {
-                const int32_t i = L.map[sl];
-                uid[j] = L.uid[i];
-                col_val[j] = __builtin_nontemporal_load(col + (L.base[i] + e0 + sl));
-            }
+            const int32_t sl0 = threadIdx.x + j * kWG;
+            ok[j] = sl0 < n_e;
+            const int32_t sl = ok[j] ? sl0 : n_e - 1;
+            eidx[j] = e0 + sl0;
+            const int32_t i = L.map[sl];
+            uid[j] = L.uid[i];
+            col_val[j] = __builtin_nontemporal_load(col + (L.base[i] + e0 + sl));
         }
     } else {
         // More entries than the staging holds (low-degree or zero-degree

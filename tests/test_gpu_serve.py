@@ -167,3 +167,81 @@ def test_serve_deep_grid(bfsmi):
     for t, r in zip(ts, (0, 299, 150, 599)):
         assert np.array_equal(res[t][0], oracle.bfs(g.off, g.col, r).level)
     bfsmi.bfs_server_destroy(s)
+
+
+def drain_completed(p, s, tickets, timeout=60.0):
+    """Collect tickets from the completion queue until all have been
+    reported; every ticket must be reported exactly once."""
+    seen = []
+    t0 = time.time()
+    while len(seen) < len(tickets):
+        seen += p.bfs_server_completed(s)
+        assert time.time() - t0 < timeout, "queries did not finish"
+        time.sleep(0.0005)
+    assert sorted(seen) == sorted(tickets)
+    assert p.bfs_server_completed(s) == []
+    return seen
+
+
+def test_serve_completion_queue_and_device_delivery(bfsmi, pool):
+    graphs, handles = pool
+    s, ids, arena = make_server(bfsmi, handles)
+    rng = np.random.default_rng(21)
+    qs = []
+    for k in range(40):
+        gi = int(rng.integers(0, len(graphs)))
+        qs.append((gi, int(rng.integers(0, graphs[gi].V))))
+    ts = [bfsmi.bfs_submit(s, ids[gi], r) for gi, r in qs]
+    drain_completed(bfsmi, s, ts)
+    for k, (t, (gi, r)) in enumerate(zip(ts, qs)):
+        g = graphs[gi]
+        if k % 2:
+            dst = torch.full((g.V,), 7, dtype=torch.int32, device="cuda")
+            code, tm = bfsmi.bfs_poll(s, t, dst)
+            got = dst.cpu().numpy()
+        else:
+            got = np.full(g.V, 7, dtype=np.int32)
+            code, tm = bfsmi.bfs_poll(s, t, got)
+        assert code == bfsmi.BFS_OK
+        ref = oracle.bfs(g.off, g.col, r)
+        assert np.array_equal(got, ref.level), (k, gi, r)
+        assert tm.levels == int(ref.level.max()) + 1
+        assert tm.submit_ns <= tm.admit_ns <= tm.done_ns
+    st = bfsmi.bfs_server_get_stats(s)
+    assert st.submitted == 40 and st.completed == 40 and st.failed == 0
+    assert st.joins == 40 and st.levels >= st.rounds > 0
+    assert st.lane_levels >= st.levels and st.device_ms > 0
+    assert 0 < st.arena_peak <= arena.numel()
+    bfsmi.bfs_server_destroy(s)
+
+
+def test_serve_staggered_arrivals_shallow_and_deep(bfsmi):
+    # graphs above the small-graph size: R-MAT (waves) and a 300 x 300 grid
+    # (continuous joins once its lane lifetime is known); queries arrive
+    # while earlier ones are on the device
+    graphs = [graphgen.rmat(17, seed=9), graphgen.grid(300, 300)]
+    handles = [bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER) for g in graphs]
+    s, ids, arena = make_server(bfsmi, handles, arena_mb=1024)
+    rng = np.random.default_rng(5)
+    qs, ts = [], []
+    for wave in range(6):
+        for _ in range(12):
+            gi = int(rng.integers(0, 2))
+            r = int(graphgen.pick_roots(graphs[gi], 1, int(rng.integers(1 << 30)))[0])
+            qs.append((gi, r))
+            ts.append(bfsmi.bfs_submit(s, ids[gi], r))
+        time.sleep(0.003)
+    drain_completed(bfsmi, s, ts, timeout=120.0)
+    for t, (gi, r) in zip(ts, qs):
+        g = graphs[gi]
+        got = np.empty(g.V, dtype=np.int32)
+        code, tm = bfsmi.bfs_poll(s, t, got)
+        assert code == bfsmi.BFS_OK
+        assert np.array_equal(got, oracle.bfs(g.off, g.col, r).level), (gi, r)
+    st = bfsmi.bfs_server_get_stats(s)
+    _say("staggered: rounds %d levels %d lanes/level %.2f batches %d"
+         % (st.rounds, st.levels, st.lane_levels / max(st.levels, 1), st.batches))
+    assert st.completed == len(ts) and st.failed == 0
+    bfsmi.bfs_server_destroy(s)
+    for h in handles:
+        h.close()
