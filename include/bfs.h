@@ -66,8 +66,11 @@ extern "C" {
 #define BFS_OPT_EDGES_PER_THREAD 1 /* 1, 2, 4 or 8 frontier edges per thread    */
 #define BFS_OPT_FRONTIER_MODE    2 /* 0 auto (list/bitmap by threshold),
                                       1 list only, 2 bitmap whenever possible */
-#define BFS_OPT_LOOP_DRIVER      3 /* 0 auto, 1 host loop (one 4-byte read per
-                                      level), 2 device loop for small frontiers */
+#define BFS_OPT_LOOP_DRIVER      3 /* 0 (default) or 2: runs of small levels
+                                      (frontier <= 65536, <= 4M edges) replay
+                                      captured level graphs, one control-block
+                                      read per 8 levels; 1: every level from
+                                      the host, one read per level           */
 #define BFS_OPT_BATCH_TILE       4 /* edges per workgroup in the batch kernels:
                                       256, 512, 1024 or 2048                  */
 #define BFS_OPT_GRID_WGS         5 /* workgroups per CU for grid-stride kernels */
@@ -202,9 +205,10 @@ int bfs_submit(bfs_server *s, int32_t graph_id, int32_t root, uint64_t *ticket);
  * Poll a query.  BFS_PENDING while it runs.  On BFS_OK, if dst_levels is not
  * NULL, writes the int32[V] levels of the query's graph into it (-1 =
  * unreached), fills *t if not NULL, and retires the ticket.  dst_levels may
- * be host memory or device memory of the server's device (a device buffer
- * is filled by a widening kernel and never crosses PCIe).  The call returns
- * after the copy is complete.  BFS_ERR_TICKET for unknown or retired
+ * be host memory or device memory of the server's device.  A device buffer
+ * is filled by a widening kernel on the device's default (null) stream, so
+ * it is ordered after work the caller queued there, and never crosses
+ * PCIe.  The call returns after the levels are written.  BFS_ERR_TICKET for unknown or retired
  * tickets.
  */
 int bfs_poll(bfs_server *s, uint64_t ticket, int32_t *dst_levels, bfs_timing *t);

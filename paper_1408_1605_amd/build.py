@@ -37,8 +37,11 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
               "-Wall", "-Wno-unused-result"]
+    # the kernels aggregate their counter atomics per wave themselves; the
+    # compiler's atomic rewrite would read each result back at once and
+    # stall the expansion pipeline
     gpu = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-munsafe-fp-atomics"]
+           "-munsafe-fp-atomics", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
     procs = []
     for src in sources():
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")

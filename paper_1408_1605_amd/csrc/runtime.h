@@ -76,6 +76,8 @@ struct bfs_graph {
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
     hipGraphExec_t ms_graph = nullptr;  // captured batch levels
     int ms_graph_ept = 0;
+    hipGraphExec_t dev_graph[2] = {nullptr, nullptr};  // single-root device loop, by queue parity
+    int dev_graph_ept = 0;
     int32_t* h_roots = nullptr;         // pinned staging for batch roots
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing
@@ -83,7 +85,7 @@ struct bfs_graph {
     // options
     int ept = 4;
     int frontier_mode = 0;  // 0 auto, 1 list only, 2 bitmap whenever possible
-    int loop_driver = 0;    // 0 auto, 1 host, 2 device loop for small frontiers
+    int loop_driver = 0;    // 0 auto (device loop for small frontiers), 1 host only
     int batch_tile = 1024;  // edges per workgroup in the batch expansion
     int grid_wgs = 8;
     int profile = 0;

@@ -677,15 +677,17 @@ int bfs_poll(bfs_server* s, uint64_t ticket, int32_t* dst_levels, bfs_timing* tm
         (void)hipGetLastError();
         hipError_t e;
         if (on_device) {
-            e = hipMemsetAsync(s->d_max, 0xff, sizeof(int32_t), s->poll_stream);
+            // the device's default stream: ordered after whatever the caller
+            // queued there for this buffer
+            hipStream_t ds = nullptr;
+            e = hipMemsetAsync(s->d_max, 0xff, sizeof(int32_t), ds);
             if (e == hipSuccess) {
                 const int grid = (int)std::min<int64_t>(((int64_t)V + 4095) / 4096, 1024);
-                e = launch_widen16(s->poll_stream, std::max(grid, 1), q.result, dst_levels, V, s->d_max);
+                e = launch_widen16(ds, std::max(grid, 1), q.result, dst_levels, V, s->d_max);
             }
             if (e == hipSuccess)
-                e = hipMemcpyAsync(s->h_max, s->d_max, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                   s->poll_stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(s->poll_stream);
+                e = hipMemcpyAsync(s->h_max, s->d_max, sizeof(int32_t), hipMemcpyDeviceToHost, ds);
+            if (e == hipSuccess) e = hipStreamSynchronize(ds);
             levels = *s->h_max + 1;
         } else {
             e = hipMemcpyAsync(s->h_stage, q.result, (size_t)V * 2, hipMemcpyDeviceToHost,

@@ -92,14 +92,20 @@ def test_rmat16_modes_ept(bfsmi, rmat16, mode, ept):
         check(bfsmi, g, G, int(r), mode=mode, ept=ept)
 
 
-def test_rmat16_sixteen_roots_auto(bfsmi, rmat16):
+@pytest.mark.parametrize("driver", [1, 0])
+def test_rmat16_sixteen_roots_auto(bfsmi, rmat16, driver):
     g, G = rmat16
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, driver)
     roots = graphgen.pick_roots(g, 16, graphgen.root_seed(16))
     nb = 0
     for r in roots:
         st = check(bfsmi, g, G, int(r))
         nb += st.bitmap_levels
-    assert nb > 0  # R-MAT frontiers cross T = V/32 at their peak
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 0)
+    if driver == 1:
+        assert nb > 0  # R-MAT frontiers cross T = V/32 at their peak
+    else:
+        assert nb == 0  # every level of this small graph stays in the device loop
 
 
 def test_isolated_root(bfsmi, rmat16):
@@ -212,9 +218,11 @@ def test_visited_summary_odd_sizes(bfsmi):
         src = np.arange(n - 1)
         g = graphgen.from_edges(n, np.zeros(n - 1, np.int64), src + 1)   # star
         G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
-        for r in (0, n - 1):
-            for mode in (0, 2):
-                check(bfsmi, g, G, r, mode=mode)
+        for summary in (1, 2):
+            G.set_option(bfsmi.BFS_OPT_VISITED_SUMMARY, summary)
+            for r in (0, n - 1):
+                for mode in (0, 2):
+                    check(bfsmi, g, G, r, mode=mode)
 
 
 @pytest.mark.skipif(os.environ.get("BFSMI_BIG", "1") == "0", reason="large graphs disabled")
@@ -224,3 +232,34 @@ def test_rmat20_parity(bfsmi, dord):
     G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER if dord else 0)
     for r in graphgen.pick_roots(g, 3, graphgen.root_seed(20)):
         check(bfsmi, g, G, int(r))
+
+
+@pytest.mark.parametrize("driver", [0, 1])
+def test_loop_driver_equivalence(bfsmi, driver):
+    # the device loop replays captured levels (8 per replay) while frontiers
+    # are small and hands heavy levels back to the host; both drivers must
+    # give the oracle's levels, sizes and a valid tree
+    cases = [graphgen.grid(300, 300), graphgen.grid(1000, 3), graphgen.rmat(18)]
+    for g in cases:
+        G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+        G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, driver)
+        roots = [0, g.V - 1] if g.name.startswith("grid") else \
+            [int(r) for r in graphgen.pick_roots(g, 2, 33)]
+        for r in roots:
+            st = check(bfsmi, g, G, r)
+            if driver == 1:
+                assert st.device_loop_levels == 0
+            elif g.name.startswith("grid"):
+                assert st.device_loop_levels >= st.levels - 2
+        G.close()
+
+
+def test_device_loop_hands_back_heavy_level(bfsmi):
+    # scale 20: the level after the root's neighbours exceeds the device
+    # loop's edge limit, so the search moves device -> host -> device
+    g = graphgen.rmat(20)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    for r in graphgen.pick_roots(g, 3, 44):
+        st = check(bfsmi, g, G, int(r))
+        assert 0 < st.device_loop_levels < st.levels
+    G.close()
