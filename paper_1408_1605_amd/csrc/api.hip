@@ -13,6 +13,11 @@
 
 namespace bfsmi {
 
+constexpr int32_t kSmallQ = 1 << 16;  // frontiers up to this size may run in the persistent loop
+constexpr int32_t kSmallDeg = 8192;   // ... if no frontier vertex has a larger degree
+constexpr int kSmallWGs = 64;         // workgroups of the persistent loop
+
+
 static thread_local char g_err[512] = "";
 
 int fail(int code, const char* fmt, ...)
@@ -61,6 +66,7 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
     L.tile_k = take((ntile_max + 2) * 4);
     L.ctrl = take(sizeof(Ctrl));
     L.scratch = take(256);
+    L.sync = take(sizeof(SmallSync));
     L.summary = take(kSummaryMaxWords * 4);
     if (flags & BFS_WS_BATCH) {
         L.ms_seen = take((size_t)V * 8);
@@ -154,6 +160,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     g->tile_k = reinterpret_cast<int32_t*>(g->ws + L.tile_k);
     g->ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ctrl);
     g->scratch = reinterpret_cast<int32_t*>(g->ws + L.scratch);
+    g->small_sync = reinterpret_cast<SmallSync*>(g->ws + L.sync);
     g->summary = reinterpret_cast<uint32_t*>(g->ws + L.summary);
     {
         // blocks of 2^shift ids, at most kSummaryMaxWords * 32 of them
@@ -193,6 +200,13 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         return cleanup(fail(BFS_ERR_HIP, "hipGetDeviceProperties failed"));
     }
     g->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    {
+        // the persistent small-level loop needs all its workgroups resident
+        const int per_cu = small_loop_blocks();
+        g->small_grid = prop.cooperativeLaunch && per_cu > 0
+                            ? std::min(kSmallWGs, per_cu * g->num_cus)
+                            : 0;
+    }
 
     // pinned host block: [Ctrl][Ctrl for the batch][64 batch roots]
     hipError_t e = hipHostMalloc((void**)&g->h_ctrl, 2 * sizeof(Ctrl) + 64 * sizeof(int32_t),
@@ -260,8 +274,6 @@ int bfs_graph_destroy(bfs_graph* g)
 {
     if (!g) return ok();
     if (g->ms_graph) (void)hipGraphExecDestroy(g->ms_graph);
-    for (auto& x : g->dev_graph)
-        if (x) (void)hipGraphExecDestroy(x);
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->h_ctrl) (void)hipHostFree(g->h_ctrl);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
@@ -370,50 +382,6 @@ static float event_ms(hipEvent_t a, hipEvent_t b)
     return ms;
 }
 
-int ensure_cap_stream(bfs_graph* g);  // batch_api.hip
-
-constexpr int kDevLevelsPerGraph = 8;       // even: the queue buffers alternate
-constexpr int32_t kDevEnterQ = 1 << 16;     // frontiers this small enter the device loop
-constexpr int64_t kDevMaxEdges = 1ll << 22; // a level with more edges leaves it
-
-// Capture kDevLevelsPerGraph device-loop levels starting from queue q[parity].
-static int capture_dev_graphs(bfs_graph* g)
-{
-    if (g->dev_graph[0] && g->dev_graph_ept == g->ept) return BFS_OK;
-    for (auto& x : g->dev_graph)
-        if (x) {
-            (void)hipGraphExecDestroy(x);
-            x = nullptr;
-        }
-    int rc = ensure_cap_stream(g);
-    if (rc != BFS_OK) return rc;
-    const int64_t tile_cap = (g->nnz + kMinTile - 1) / kMinTile + 1;
-    const int xgrid = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, 0));
-    const int sgrid = g->num_cus * 2;
-    hipStream_t s = g->cap_stream;
-    for (int p = 0; p < 2; ++p) {
-        BFS_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int j = 0; j < kDevLevelsPerGraph && e == hipSuccess; ++j) {
-            const int q = (p + j) & 1;
-            e = launch_dev_level(s, sgrid, xgrid, g->ept, g->V, tile_cap, g->s_off, g->s_col,
-                                 g->orig, g->q[q], g->q[q ^ 1], g->deg, g->rowstart, g->suid,
-                                 g->bsum, g->cumul, g->tile_k, g->vis, g->vis_old, g->ctrl);
-        }
-        hipGraph_t graph = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(s, &graph);
-        if (e == hipSuccess && e2 == hipSuccess)
-            e = hipGraphInstantiate(&g->dev_graph[p], graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            g->dev_graph[p] = nullptr;
-            return hip_fail(e != hipSuccess ? e : e2, "device loop capture");
-        }
-    }
-    g->dev_graph_ept = g->ept;
-    return BFS_OK;
-}
-
 // The level loop for one root: heavy levels are driven from the host (one
 // control-block read per level, per-level choices of summary and frontier
 // form); runs of small levels go to the device loop.
@@ -445,34 +413,29 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
     int cur = 0;
     int64_t reached = 1, edges = 0, xbytes = 0;
     int32_t nlevels = 1, bitmap_levels = 0, xlaunches = 0, dev_levels = 0;
-    const bool dev_ok = g->loop_driver != 1;
-    if (dev_ok) {
-        const int rc = capture_dev_graphs(g);
-        if (rc != BFS_OK) return rc;
-    }
-    bool dev_left = false;  // the device loop just handed a heavy level back
+    const bool dev_ok = g->loop_driver != 1 && g->small_grid > 0;
+    bool dev_left = false;  // the persistent loop just handed a heavy level back
     while (true) {
-        if (dev_ok && !dev_left && qlen <= kDevEnterQ) {
-            BFS_HIP_TRY(launch_dev_enter(s, g->ctrl, qlen, lvl, kDevMaxEdges, levels, parents));
-            int32_t steps = 0;
-            while (true) {
-                BFS_HIP_TRY(hipGraphLaunch(g->dev_graph[(cur + steps) & 1], s));
-                BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-                BFS_HIP_TRY(hipStreamSynchronize(s));
-                steps = g->h_ctrl->steps;
-                if (g->h_ctrl->done) break;
-            }
+        if (dev_ok && !dev_left && qlen <= kSmallQ) {
+            BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
+            BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
+            BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
+                                            g->vis, g->vis_old, g->q[cur], g->q[cur ^ 1], levels,
+                                            parents, g->small_sync, g->ctrl, qlen, lvl, kSmallQ,
+                                            (int64_t)g->small_grid * kSmallDeg, kSmallDeg));
+            BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+            BFS_HIP_TRY(hipStreamSynchronize(s));
             const Ctrl& c = *g->h_ctrl;
             if (c.err) return fail(BFS_ERR_HIP, "internal guard tripped (code %d)", c.err);
             reached += c.reached;
             nlevels += c.levels;
             edges += c.r_total;
-            dev_levels += steps;
-            cur = (cur + steps) & 1;
+            dev_levels += c.steps;
+            cur = (cur + c.steps) & 1;
             lvl = c.level;
             qlen = c.qlen;
             if (c.done == 1) break;  // the frontier ran empty
-            dev_left = true;         // done == 2: this level is the host's
+            dev_left = true;         // done == 2: the next level is the host's
             continue;
         }
         dev_left = false;

@@ -37,12 +37,9 @@ struct alignas(64) Ctrl {
     uint64_t alive;      // batch: OR of the lanes that found vertices this level
     uint64_t last_alive; // batch: alive of the last completed level
     int8_t* out8;        // batch: output rows (read by the device each launch)
-    // single-root device loop (levels replayed from a captured graph)
-    int64_t rlimit;      // a level with more edges ends the device loop (done = 2)
-    int32_t steps;       // levels completed in the device loop
+    // single-root persistent loop (smallloop.hip)
+    int32_t steps;       // levels completed in the loop
     int32_t pad3;
-    int32_t* out_level;  // output arrays of the current search
-    int32_t* out_parent;
 };
 
 // ---- single-root kernels (frontier.hip) ----
@@ -75,16 +72,21 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
 
 // Visited summary before a heavy level: ctrl->full_prefix and one bit per
 // block of 2^shift ids (set when the whole block is visited).
-// Single-root device loop: k_dev_enter starts it from the host's state,
-// launch_dev_level enqueues one level (scan, expansion in list form, step)
-// whose kernels all read their sizes from ctrl and return once done != 0.
-hipError_t launch_dev_enter(hipStream_t s, Ctrl* ctrl, int32_t qlen, int32_t level,
-                            int64_t rlimit, int32_t* out_level, int32_t* out_parent);
-hipError_t launch_dev_level(hipStream_t s, int scan_grid, int expand_grid, int ept, int32_t V,
-                            int64_t tile_cap, const int64_t* off, const int32_t* col,
-                            const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
-                            int64_t* rowstart, int32_t* uidv, int64_t* bsum, int64_t* cumul,
-                            int32_t* tile_k, uint32_t* vis, uint32_t* vis_old, Ctrl* ctrl);
+// Single-root persistent loop for runs of small levels (smallloop.hip).
+// Zeroed by the host before each launch.
+struct SmallSync {
+    uint32_t arrive;   // grid barrier: workgroups arrived
+    uint32_t gen;      // grid barrier: generation
+    uint32_t qn[3];    // next-frontier size, by level mod 3
+    int32_t md[3];     // largest degree in the next frontier
+    int64_t rn[3];     // edges of the next frontier
+};
+int small_loop_blocks();
+hipError_t launch_small_levels(hipStream_t s, int grid, int32_t V, const int64_t* off,
+                               const int32_t* col, const int32_t* orig, uint32_t* vis,
+                               uint32_t* vis_old, int32_t* Qa, int32_t* Qb, int32_t* level,
+                               int32_t* parent, SmallSync* sy, Ctrl* ctrl, int32_t qlen,
+                               int32_t lvl, int32_t qlimit, int64_t rlimit, int32_t dlimit);
 
 hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
                                   const uint32_t* vis, int32_t shift, int32_t nblocks,

@@ -167,10 +167,6 @@ __global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, in
     }
     if (threadIdx.x == 0) {
         int64_t r = carry;
-        if (dev && ctrl->rlimit > 0 && r > ctrl->rlimit) {
-            ctrl->done = 2;  // too heavy for the device loop: back to the host
-            return;
-        }
         int64_t nt = (r + tile - 1) / tile;
         if (nt > tile_cap) {  // more edges than the graph holds: refuse
             ctrl->err = 1;
@@ -417,13 +413,6 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
     __shared__ TileLds<EPT> L;
     extern __shared__ uint32_t s_sum[];
 
-    if (lvl < 0) {
-        // device loop: outputs and depth come from the control block
-        if (ctrl->done) return;
-        level = ctrl->out_level;
-        parent = ctrl->out_parent;
-        lvl = ctrl->level;
-    }
     const int64_t r = ctrl->r;
     const int32_t ntiles = ctrl->ntiles;
     const bool list_out = ctrl->bitmap_out == 0;
@@ -550,66 +539,6 @@ int expand_blocks_per_cu(int ept, int summary_words)
     }
     if (e != hipSuccess || n < 1) n = 1;
     return n;
-}
-
-// ---------------------------------------------------------------------------
-// Single-root device loop.  Levels whose frontiers are small cost little on
-// the device; their host round trip would dominate (a 4096 x 4096 grid has
-// thousands of such levels).  These levels are replayed from a captured
-// graph; the step kernel advances the control block, and the host reads it
-// once per replay.
-
-__global__ void k_dev_enter(Ctrl* __restrict__ ctrl, int32_t qlen, int32_t level, int64_t rlimit,
-                            int32_t* out_level, int32_t* out_parent)
-{
-    ctrl->qlen = qlen;
-    ctrl->level = level;
-    ctrl->done = 0;
-    ctrl->qn_count = 0;
-    ctrl->bitmap_out = 0;
-    ctrl->rlimit = rlimit;
-    ctrl->steps = 0;
-    ctrl->reached = 0;
-    ctrl->levels = 0;
-    ctrl->r_total = 0;
-    ctrl->out_level = out_level;
-    ctrl->out_parent = out_parent;
-}
-
-__global__ void k_dev_step(Ctrl* __restrict__ ctrl)
-{
-    if (ctrl->done) return;
-    const uint32_t q = ctrl->qn_count;
-    ctrl->reached += q;
-    ctrl->qlen = (int32_t)q;
-    if (q) ctrl->levels += 1;
-    ctrl->level += 1;
-    ctrl->steps += 1;
-    ctrl->done = (q == 0 || ctrl->err) ? 1 : 0;
-}
-
-hipError_t launch_dev_enter(hipStream_t s, Ctrl* ctrl, int32_t qlen, int32_t level,
-                            int64_t rlimit, int32_t* out_level, int32_t* out_parent)
-{
-    hipLaunchKernelGGL(k_dev_enter, dim3(1), dim3(1), 0, s, ctrl, qlen, level, rlimit, out_level,
-                       out_parent);
-    return hipGetLastError();
-}
-
-hipError_t launch_dev_level(hipStream_t s, int scan_grid, int expand_grid, int ept, int32_t V,
-                            int64_t tile_cap, const int64_t* off, const int32_t* col,
-                            const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
-                            int64_t* rowstart, int32_t* uidv, int64_t* bsum, int64_t* cumul,
-                            int32_t* tile_k, uint32_t* vis, uint32_t* vis_old, Ctrl* ctrl)
-{
-    hipError_t e = launch_scan_dev(s, scan_grid, Q, off, orig, deg, rowstart, uidv, bsum, cumul,
-                                   tile_k, tile_cap, kWG * ept, ctrl);
-    if (e != hipSuccess) return e;
-    e = launch_expand(s, ept, expand_grid, V, rowstart, uidv, cumul, tile_k, col, orig, nullptr, 0,
-                      0, 0, vis, vis_old, nullptr, nullptr, -1, Qn, ctrl);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dev_step, dim3(1), dim3(1), 0, s, ctrl);
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@ int ok();
 
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct WsLayout {
-    size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, summary;
+    size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, summary;
     size_t ms_seen, ms_front, ms_next, ms_ctrl, ms_roots, ms_touched;
     size_t rank, orig, off_r, col_r, hist;
     size_t total;
@@ -76,8 +76,8 @@ struct bfs_graph {
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
     hipGraphExec_t ms_graph = nullptr;  // captured batch levels
     int ms_graph_ept = 0;
-    hipGraphExec_t dev_graph[2] = {nullptr, nullptr};  // single-root device loop, by queue parity
-    int dev_graph_ept = 0;
+    bfsmi::SmallSync* small_sync = nullptr;  // persistent small-level loop: barrier, counters
+    int small_grid = 0;                       // its workgroups (0: not available)
     int32_t* h_roots = nullptr;         // pinned staging for batch roots
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing
@@ -85,7 +85,7 @@ struct bfs_graph {
     // options
     int ept = 4;
     int frontier_mode = 0;  // 0 auto, 1 list only, 2 bitmap whenever possible
-    int loop_driver = 0;    // 0 auto (device loop for small frontiers), 1 host only
+    int loop_driver = 0;    // 0 auto (persistent loop for runs of small levels), 1 host only
     int batch_tile = 1024;  // edges per workgroup in the batch expansion
     int grid_wgs = 8;
     int profile = 0;
