@@ -166,6 +166,8 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(const int64_t* __restrict__ r
     }
 }
 
+constexpr int kFinItems = 8;  // vertices per thread and chunk in the finalize
+
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x)
 {
     for (int d = 1; d < 64; d <<= 1) x |= __shfl_xor(x, d, 64);
@@ -186,64 +188,96 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
                                                      const int32_t* __restrict__ lane_start,
                                                      Ctrl* __restrict__ ctrl)
 {
+    constexpr int IT = kFinItems;
+    __shared__ int16_t* s_out[64];
+    __shared__ int32_t s_start[64];
+    __shared__ uint32_t s_wave[kWG / 64];
+    __shared__ uint32_t s_base;
+    __shared__ uint64_t s_alive[kWG / 64];
     if (ctrl->done) return;
     const int32_t lvl = ctrl->level;
     const bool sparse = ctrl->sparse != 0;
     int8_t* __restrict__ out8 = ctrl->out8;
-    const int64_t stride = (int64_t)gridDim.x * kWG;
+    if (OUT16) {
+        // the lane tables, once per workgroup
+        if (threadIdx.x < 64) {
+            s_out[threadIdx.x] = lane_out[threadIdx.x];
+            s_start[threadIdx.x] = lane_start[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    // A workgroup takes chunks of kWG * IT vertices; each chunk reserves its
+    // queue slots with one atomicAdd (a per-wave add on the one counter
+    // would serialise tens of thousands of atomics per level).
+    constexpr int64_t chunk = (int64_t)kWG * IT;
     uint64_t alive = 0;
-    for (int64_t base = (int64_t)blockIdx.x * kWG; base < V; base += stride) {
-        const int64_t v = base + threadIdx.x;
-        uint64_t nw = 0;
-        bool hit = v < V;
-        if (sparse && v < V) {
-            // the 32 lanes of a word read it before its first lane clears it
-            const uint32_t tw = touched[v >> 5];
-            hit = (tw >> (v & 31)) & 1u;
-            if ((v & 31) == 0 && tw) touched[v >> 5] = 0;
-        }
-        if (hit) {
-            const uint64_t n = next[v];
-            if (n) {
-                const uint64_t sv = seen[v];
-                nw = n & ~sv;
-                next[v] = 0;
-                if (nw) seen[v] = sv | nw;
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < V; c0 += (int64_t)gridDim.x * chunk) {
+        uint64_t nw[IT];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int64_t v = c0 + j * kWG + threadIdx.x;
+            nw[j] = 0;
+            bool hit = v < V;
+            if (sparse && v < V) {
+                // the 32 lanes of a word read it before its first lane clears it
+                const uint32_t tw = touched[v >> 5];
+                hit = (tw >> (v & 31)) & 1u;
+                if ((v & 31) == 0 && tw) touched[v >> 5] = 0;
             }
-            front[v] = nw;
-        }
-        const uint64_t mask = __ballot(nw != 0);
-        if (mask) {
-            uint32_t pos = 0;
-            if (__lane_id() == 0) pos = atomicAdd(&ctrl->qn_count, (uint32_t)__popcll(mask));
-            pos = __shfl(pos, 0, 64) + lanes_below(mask);
-            if (nw) {
-                if (pos < (uint32_t)V) Qn[pos] = (int32_t)v;
-                else ctrl->err = 4;
+            if (hit) {
+                const uint64_t n = next[v];
+                if (n) {
+                    const uint64_t sv = seen[v];
+                    nw[j] = n & ~sv;
+                    next[v] = 0;
+                    if (nw[j]) seen[v] = sv | nw[j];
+                }
+                front[v] = nw[j];
             }
-            const uint64_t lanes = wave_or64(nw);
-            const int64_t vo = (nw && orig) ? orig[v] : v;
+            cnt += nw[j] ? 1u : 0u;
+        }
+        uint32_t tot;
+        const uint32_t ex = wg_exclusive_scan<uint32_t>(cnt, &tot, s_wave);
+        if (tot == 0) continue;  // uniform: no queue slots, no outputs
+        if (threadIdx.x == 0) s_base = atomicAdd(&ctrl->qn_count, tot);
+        __syncthreads();
+        uint32_t pos = s_base + ex;
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            if (!nw[j]) continue;
+            const int64_t v = c0 + j * kWG + threadIdx.x;
+            if (pos < (uint32_t)V) Qn[pos] = (int32_t)v;
+            else ctrl->err = 4;
+            ++pos;
+            // each vertex writes only the lanes that reached it now
+            const int64_t vo = orig ? orig[v] : v;
             if (OUT16) {
-                for (uint64_t m = lanes; m; m &= m - 1) {
+                for (uint64_t m = nw[j]; m; m &= m - 1) {
                     const int b = __builtin_ctzll(m);
-                    if ((nw >> b) & 1ull) {
-                        const int32_t d = lvl - lane_start[b];
-                        if (d > 32767) ctrl->overflow = 1;
-                        else lane_out[b][vo] = (int16_t)d;
-                    }
+                    const int32_t d = lvl - s_start[b];
+                    if (d > 32767) ctrl->overflow = 1;
+                    else s_out[b][vo] = (int16_t)d;
                 }
             } else if (lvl > 127) {
-                if (nw) ctrl->overflow = 1;
+                ctrl->overflow = 1;
             } else {
-                for (uint64_t m = lanes; m; m &= m - 1) {
-                    const int b = __builtin_ctzll(m);
-                    if ((nw >> b) & 1ull) out8[(int64_t)b * V + vo] = (int8_t)lvl;
-                }
+                for (uint64_t m = nw[j]; m; m &= m - 1)
+                    out8[(int64_t)__builtin_ctzll(m) * V + vo] = (int8_t)lvl;
             }
-            alive |= lanes;
+            alive |= nw[j];
         }
+        __syncthreads();  // s_base is rewritten by the next chunk
     }
-    if (__lane_id() == 0 && alive) atomicOr((unsigned long long*)&ctrl->alive, (unsigned long long)alive);
+    // one alive update per workgroup
+    alive = wave_or64(alive);
+    if (__lane_id() == 0) s_alive[threadIdx.x >> 6] = alive;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0;
+        for (int w = 0; w < kWG / 64; ++w) a |= s_alive[w];
+        if (a) atomicOr((unsigned long long*)&ctrl->alive, (unsigned long long)a);
+    }
 }
 
 // Sparse levels: the old frontier's masks are cleared through the queue
