@@ -69,9 +69,8 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
     L.sync = take(sizeof(SmallSync));
     L.summary = take(kSummaryMaxWords * 4);
     if (flags & BFS_WS_BATCH) {
-        L.ms_seen = take((size_t)V * 8);
+        L.ms_sn = take((size_t)V * 16);
         L.ms_front = take((size_t)V * 8);
-        L.ms_next = take((size_t)V * 8);
         L.ms_ctrl = take(sizeof(Ctrl));
         L.ms_roots = take(64 * 4);
         L.ms_touched = take(W * 4);
@@ -179,9 +178,8 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         g->s_col = reinterpret_cast<int32_t*>(g->ws + L.col_r);
     }
     if (flags & BFS_WS_BATCH) {
-        g->ms_seen = reinterpret_cast<uint64_t*>(g->ws + L.ms_seen);
+        g->ms_sn = reinterpret_cast<SeenNext*>(g->ws + L.ms_sn);
         g->ms_front = reinterpret_cast<uint64_t*>(g->ws + L.ms_front);
-        g->ms_next = reinterpret_cast<uint64_t*>(g->ws + L.ms_next);
         g->ms_ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ms_ctrl);
         g->ms_roots = reinterpret_cast<int32_t*>(g->ws + L.ms_roots);
         g->ms_touched = reinterpret_cast<uint32_t*>(g->ws + L.ms_touched);

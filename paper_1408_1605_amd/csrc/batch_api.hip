@@ -47,7 +47,7 @@ static hipError_t enqueue_level(bfs_graph* g, hipStream_t s, const BatchGrids& b
     return launch_ms_level(s, b.scan, b.expand, b.fin, b.ept, g->V, b.tile_cap, g->s_off, g->s_col,
                            g->orig, g->q[parity], g->q[parity ^ 1], g->deg, g->rowstart, g->suid,
                            g->bsum, g->cumul,
-                           g->tile_k, g->ms_seen, g->ms_front, g->ms_next, g->ms_touched, nullptr,
+                           g->tile_k, g->ms_sn, g->ms_front, g->ms_touched, nullptr,
                            nullptr, g->ms_ctrl);
 }
 
@@ -122,7 +122,7 @@ extern "C" int bfs_run_batch(bfs_graph* g, const int32_t* h_roots, int32_t n_roo
     if (!h_roots) return fail(BFS_ERR_INVALID, "roots pointer is NULL");
     if (n_roots < 1 || n_roots > 64) return fail(BFS_ERR_INVALID, "n_roots must be 1..64 (got %d)", n_roots);
     if (!d_levels) return fail(BFS_ERR_INVALID, "levels pointer is NULL");
-    if (!g->ms_seen) return fail(BFS_ERR_INVALID, "graph was created without BFS_WS_BATCH");
+    if (!g->ms_sn) return fail(BFS_ERR_INVALID, "graph was created without BFS_WS_BATCH");
     for (int i = 0; i < n_roots; ++i)
         if (h_roots[i] < 0 || h_roots[i] >= g->V)
             return fail(BFS_ERR_INVALID, "root %d (index %d) outside [0, %d)", h_roots[i], i, g->V);
@@ -140,8 +140,8 @@ extern "C" int bfs_run_batch(bfs_graph* g, const int32_t* h_roots, int32_t n_roo
     BFS_HIP_TRY(hipEventRecord(g->ev0, s));
     BFS_HIP_TRY(hipMemcpyAsync(g->ms_roots, g->h_roots, sizeof(int32_t) * (size_t)n_roots,
                                hipMemcpyHostToDevice, s));
-    BFS_HIP_TRY(launch_ms_init(s, g->num_cus * 8, g->V, g->ms_roots, n_roots, g->rank, g->ms_seen,
-                               g->ms_front, g->ms_next, g->ms_touched, d_levels, g->q[0],
+    BFS_HIP_TRY(launch_ms_init(s, g->num_cus * 8, g->V, g->ms_roots, n_roots, g->rank, g->ms_sn,
+                               g->ms_front, g->ms_touched, d_levels, g->q[0],
                                g->ms_ctrl));
     const bool use_graph = g->loop_driver != 1;
     if (use_graph) {

@@ -104,19 +104,24 @@ hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
 // orig[rank[v]] = v; off_r / col_r is the CSR in internal ids (row x is
 // the row of orig[x], neighbours mapped through rank).
 // ---- multi-source batch (msbfs.hip) ----
+// The two masks of a vertex that the expansion tests together.
+struct alignas(16) SeenNext {
+    uint64_t seen;  // lanes that reached the vertex
+    uint64_t next;  // lanes that found it during the current level
+};
+
 // Lanes are bits of a 64-bit mask per vertex: seen (reached), front (this
 // level's frontier), next (found during this level).  All launches read
 // their sizes from ctrl and return at once when ctrl->done is set.
 hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* h_roots_dev,
-                          int32_t n_roots, const int32_t* rank, uint64_t* seen, uint64_t* front,
-                          uint64_t* next, uint32_t* touched, int8_t* out8, int32_t* Q,
-                          Ctrl* ctrl);
+                          int32_t n_roots, const int32_t* rank, SeenNext* sn, uint64_t* front,
+                          uint32_t* touched, int8_t* out8, int32_t* Q, Ctrl* ctrl);
 hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid,
                            int ept, int32_t V, int64_t tile_cap, const int64_t* off,
                            const int32_t* col, const int32_t* orig, const int32_t* Q,
                            int32_t* Qn, int32_t* deg, int64_t* rowstart, int32_t* uidv,
                            int64_t* bsum, int64_t* cumul,
-                           int32_t* tile_k, uint64_t* seen, uint64_t* front, uint64_t* next,
+                           int32_t* tile_k, SeenNext* sn, uint64_t* front,
                            uint32_t* touched, int16_t* const* lane_out,
                            const int32_t* lane_start, Ctrl* ctrl);
 int ms_expand_blocks_per_cu(int ept);
@@ -124,14 +129,14 @@ int ms_expand_blocks_per_cu(int ept);
 // Serving lanes (msbfs.hip).  lane_out: device table of 64 int16 result
 // pointers; lane_start: device int32[64]; join: device int32 pairs
 // (root, lane).
-hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t* front,
-                            uint64_t* next, uint32_t* touched, Ctrl* ctrl);
-hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t mask);
+hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, SeenNext* sn, uint64_t* front,
+                            uint32_t* touched, Ctrl* ctrl);
+hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, SeenNext* sn, uint64_t mask);
 hipError_t launch_fill16(hipStream_t s, int grid, int16_t* p, int64_t n, int16_t val);
 hipError_t launch_widen16(hipStream_t s, int grid, const int16_t* src, int32_t* dst, int64_t n,
                           int32_t* maxp);
 hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32_t* join,
-                           const int32_t* rank, uint64_t* seen, uint64_t* front,
+                           const int32_t* rank, SeenNext* sn, uint64_t* front,
                            int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl);
 
 hipError_t build_degree_order(hipStream_t s, int32_t V, int64_t nnz, const int64_t* off,

@@ -2,11 +2,13 @@
 //
 // Lane b of a 64-bit mask per vertex belongs to root b.  seen[v] holds the
 // lanes that reached v, front[v] the lanes for which v is in this level's
-// frontier, next[v] the lanes that found v during this level.  A level is
+// frontier, next[v] the lanes that found v during this level; seen and next
+// sit side by side (SeenNext), so one 16-byte load tests both.  A level is
 // the paper's frontier expansion (Section 3.4) run once over the union
 // frontier {v : front[v] != 0}: the same degree scan and edge -> thread
 // mapping, with the visited test and claim done on whole masks,
-//   next[v] |= front[u] & ~seen[v]   (64-bit atomic OR, no return value),
+//   next[v] |= front[u] & ~(seen[v] | next[v])   (64-bit atomic OR, no
+//   return value, skipped when no lane is new),
 // then a finalize pass turns next into the new frontier (new = next & ~seen),
 // writes level L into row b of the output for every new lane b, and
 // compacts the union frontier.  Lanes never interact, so each row equals the
@@ -28,18 +30,16 @@
 namespace bfsmi {
 
 __global__ __launch_bounds__(kWG) void k_ms_clear(int32_t V, int32_t n_roots,
-                                                  uint64_t* __restrict__ seen,
+                                                  SeenNext* __restrict__ sn,
                                                   uint64_t* __restrict__ front,
-                                                  uint64_t* __restrict__ next,
                                                   uint32_t* __restrict__ touched,
                                                   int8_t* __restrict__ out8, int vec)
 {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     const int64_t tid = (int64_t)blockIdx.x * kWG + threadIdx.x;
     for (int64_t v = tid; v < V; v += stride) {
-        seen[v] = 0;
+        sn[v] = SeenNext{0ull, 0ull};
         front[v] = 0;
-        next[v] = 0;
     }
     for (int64_t w = tid; w < ((int64_t)V + 31) / 32; w += stride) touched[w] = 0;
     const int64_t nbytes = (int64_t)n_roots * V;
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kWG) void k_ms_clear(int32_t V, int32_t n_roots,
 __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
                                                   const int32_t* __restrict__ roots,
                                                   const int32_t* __restrict__ rank,
-                                                  uint64_t* __restrict__ seen,
+                                                  SeenNext* __restrict__ sn,
                                                   uint64_t* __restrict__ front,
                                                   int8_t* __restrict__ out8,
                                                   int32_t* __restrict__ Q,
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
             }
         }
         if (first) {
-            seen[x] = lanes;
+            sn[x].seen = lanes;
             front[x] = lanes;
             Q[atomicAdd(&s_n, 1)] = x;
         }
@@ -110,14 +110,14 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
 }
 
 hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* roots_dev,
-                          int32_t n_roots, const int32_t* rank, uint64_t* seen, uint64_t* front,
-                          uint64_t* next, uint32_t* touched, int8_t* out8, int32_t* Q, Ctrl* ctrl)
+                          int32_t n_roots, const int32_t* rank, SeenNext* sn, uint64_t* front,
+                          uint32_t* touched, int8_t* out8, int32_t* Q, Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
     const int vec = ((uintptr_t)out8 % 16) == 0;
-    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, n_roots, seen, front, next,
-                       touched, out8, vec);
-    hipLaunchKernelGGL(k_ms_roots, dim3(1), dim3(64), 0, s, V, n_roots, roots_dev, rank, seen, front,
+    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, n_roots, sn, front, touched,
+                       out8, vec);
+    hipLaunchKernelGGL(k_ms_roots, dim3(1), dim3(64), 0, s, V, n_roots, roots_dev, rank, sn, front,
                        out8, Q, ctrl);
     return hipGetLastError();
 }
@@ -129,8 +129,7 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(const int64_t* __restrict__ r
                                                    const int32_t* __restrict__ tile_k,
                                                    const int32_t* __restrict__ col,
                                                    const uint64_t* __restrict__ front,
-                                                   const uint64_t* __restrict__ seen,
-                                                   uint64_t* __restrict__ next,
+                                                   SeenNext* __restrict__ sn,
                                                    uint32_t* __restrict__ touched,
                                                    const Ctrl* __restrict__ ctrl)
 {
@@ -146,16 +145,25 @@ __global__ __launch_bounds__(kWG) void k_ms_expand(const int64_t* __restrict__ r
         int64_t ee[EPT];
         map_tile<EPT>(L, cur, r, cumul, rowstart, uidv, col, uu, vv, ok, ee);
         cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
-        uint64_t f[EPT], sn[EPT];
+        // one 16-byte load gives both masks of the target: lanes that have
+        // seen it, and lanes already recorded for the next level (a stale
+        // pair only lets more threads issue the atomic)
+        uint64_t f[EPT], have[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) f[j] = ok[j] ? front[uu[j]] : 0ull;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) sn[j] = f[j] ? seen[vv[j]] : ~0ull;
+        for (int j = 0; j < EPT; ++j) {
+            have[j] = ~0ull;
+            if (f[j]) {
+                const SeenNext p = sn[vv[j]];
+                have[j] = p.seen | p.next;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const uint64_t nb = f[j] & ~sn[j];
+            const uint64_t nb = f[j] & ~have[j];
             if (nb) {
-                (void)__hip_atomic_fetch_or(next + vv[j], nb, __ATOMIC_RELAXED,
+                (void)__hip_atomic_fetch_or(&sn[vv[j]].next, nb, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
                 if (sparse)
                     (void)__hip_atomic_fetch_or(touched + (vv[j] >> 5), 1u << (vv[j] & 31),
@@ -179,9 +187,8 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x)
 //                its own int16 buffer lane_out[b] (caller ids).
 template <bool OUT16>
 __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* __restrict__ orig,
-                                                     uint64_t* __restrict__ seen,
+                                                     SeenNext* __restrict__ sn,
                                                      uint64_t* __restrict__ front,
-                                                     uint64_t* __restrict__ next,
                                                      uint32_t* __restrict__ touched,
                                                      int32_t* __restrict__ Qn,
                                                      int16_t* const* __restrict__ lane_out,
@@ -226,12 +233,10 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
                 if ((v & 31) == 0 && tw) touched[v >> 5] = 0;
             }
             if (hit) {
-                const uint64_t n = next[v];
-                if (n) {
-                    const uint64_t sv = seen[v];
-                    nw[j] = n & ~sv;
-                    next[v] = 0;
-                    if (nw[j]) seen[v] = sv | nw[j];
+                const SeenNext p = sn[v];
+                if (p.next) {
+                    nw[j] = p.next & ~p.seen;
+                    sn[v] = SeenNext{p.seen | nw[j], 0ull};
                 }
                 front[v] = nw[j];
             }
@@ -310,11 +315,11 @@ __global__ void k_ms_advance(Ctrl* __restrict__ ctrl)
 template <int EPT>
 static void ms_expand_launch(hipStream_t s, int grid, const int64_t* rowstart, const int32_t* uidv,
                              const int64_t* cumul, const int32_t* tile_k, const int32_t* col,
-                             const uint64_t* front, const uint64_t* seen, uint64_t* next,
-                             uint32_t* touched, const Ctrl* ctrl)
+                             const uint64_t* front, SeenNext* sn, uint32_t* touched,
+                             const Ctrl* ctrl)
 {
     hipLaunchKernelGGL(k_ms_expand<EPT>, dim3(grid), dim3(kWG), 0, s, rowstart, uidv, cumul, tile_k,
-                       col, front, seen, next, touched, ctrl);
+                       col, front, sn, touched, ctrl);
 }
 
 int ms_expand_blocks_per_cu(int ept)
@@ -336,8 +341,7 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
                            int32_t V, int64_t tile_cap, const int64_t* off, const int32_t* col,
                            const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
                            int64_t* rowstart, int32_t* uidv, int64_t* bsum, int64_t* cumul,
-                           int32_t* tile_k, uint64_t* seen,
-                           uint64_t* front, uint64_t* next, uint32_t* touched,
+                           int32_t* tile_k, SeenNext* sn, uint64_t* front, uint32_t* touched,
                            int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl)
 {
     hipError_t e = launch_scan_dev(s, scan_grid, Q, off, nullptr, deg, rowstart, uidv, bsum, cumul,
@@ -345,20 +349,20 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
     if (e != hipSuccess) return e;
     if (expand_grid < 1) expand_grid = 1;
     switch (ept) {
-    case 1: ms_expand_launch<1>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
-    case 2: ms_expand_launch<2>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
-    case 4: ms_expand_launch<4>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
-    case 8: ms_expand_launch<8>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, seen, next, touched, ctrl); break;
+    case 1: ms_expand_launch<1>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, sn, touched, ctrl); break;
+    case 2: ms_expand_launch<2>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, sn, touched, ctrl); break;
+    case 4: ms_expand_launch<4>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, sn, touched, ctrl); break;
+    case 8: ms_expand_launch<8>(s, expand_grid, rowstart, uidv, cumul, tile_k, col, front, sn, touched, ctrl); break;
     default: return hipErrorInvalidValue;
     }
     if (fin_grid < 1) fin_grid = 1;
     hipLaunchKernelGGL(k_ms_clear_front, dim3(scan_grid), dim3(kWG), 0, s, Q, front, ctrl);
     if (lane_out) {
-        hipLaunchKernelGGL(k_ms_finalize<true>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, seen,
-                           front, next, touched, Qn, lane_out, lane_start, ctrl);
+        hipLaunchKernelGGL(k_ms_finalize<true>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, sn,
+                           front, touched, Qn, lane_out, lane_start, ctrl);
     } else {
-        hipLaunchKernelGGL(k_ms_finalize<false>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, seen,
-                           front, next, touched, Qn, lane_out, lane_start, ctrl);
+        hipLaunchKernelGGL(k_ms_finalize<false>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, sn,
+                           front, touched, Qn, lane_out, lane_start, ctrl);
     }
     hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ctrl);
     return hipGetLastError();
@@ -368,17 +372,15 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
 // Serving: lanes join a running batch at a level boundary and retire when a
 // level finds nothing for them.
 
-__global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, uint64_t* __restrict__ seen,
+__global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, SeenNext* __restrict__ sn,
                                                    uint64_t* __restrict__ front,
-                                                   uint64_t* __restrict__ next,
                                                    uint32_t* __restrict__ touched,
                                                    Ctrl* __restrict__ ctrl)
 {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < V; v += stride) {
-        seen[v] = 0;
+        sn[v] = SeenNext{0ull, 0ull};
         front[v] = 0;
-        next[v] = 0;
     }
     for (int64_t w = (int64_t)blockIdx.x * kWG + threadIdx.x; w < ((int64_t)V + 31) / 32; w += stride)
         touched[w] = 0;
@@ -403,13 +405,13 @@ __global__ __launch_bounds__(kWG) void k_srv_reset(int32_t V, uint64_t* __restri
 }
 
 // Clear the retired lanes' bits from every vertex's seen mask.
-__global__ __launch_bounds__(kWG) void k_srv_clear(int32_t V, uint64_t* __restrict__ seen,
+__global__ __launch_bounds__(kWG) void k_srv_clear(int32_t V, SeenNext* __restrict__ sn,
                                                    uint64_t mask)
 {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < V; v += stride) {
-        const uint64_t x = seen[v];
-        if (x & mask) seen[v] = x & ~mask;
+        const uint64_t x = sn[v].seen;
+        if (x & mask) sn[v].seen = x & ~mask;
     }
 }
 
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(kWG) void k_widen16(const int16_t* __restrict__ src
 // root gets depth 0; its first expansion is the next level, so
 // lane_start = level - 1.  Roots not yet in the union frontier are appended.
 __global__ void k_srv_join(int32_t V, int32_t n_join, const int32_t* __restrict__ join,
-                           const int32_t* __restrict__ rank, uint64_t* __restrict__ seen,
+                           const int32_t* __restrict__ rank, SeenNext* __restrict__ sn,
                            uint64_t* __restrict__ front, int16_t* const* __restrict__ lane_out,
                            int32_t* __restrict__ lane_start, int32_t* __restrict__ Q,
                            Ctrl* __restrict__ ctrl)
@@ -459,7 +461,7 @@ __global__ void k_srv_join(int32_t V, int32_t n_join, const int32_t* __restrict_
         const int32_t b = join[2 * i + 1];
         const int32_t x = rank ? rank[r] : r;
         const uint64_t bit = 1ull << b;
-        atomicOr((unsigned long long*)&seen[x], (unsigned long long)bit);
+        atomicOr((unsigned long long*)&sn[x].seen, (unsigned long long)bit);
         const uint64_t old = atomicOr((unsigned long long*)&front[x], (unsigned long long)bit);
         lane_out[b][r] = 0;
         lane_start[b] = ctrl->level - 1;
@@ -477,17 +479,16 @@ __global__ void k_srv_join(int32_t V, int32_t n_join, const int32_t* __restrict_
     }
 }
 
-hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t* front,
-                            uint64_t* next, uint32_t* touched, Ctrl* ctrl)
+hipError_t launch_srv_reset(hipStream_t s, int grid, int32_t V, SeenNext* sn, uint64_t* front,
+                            uint32_t* touched, Ctrl* ctrl)
 {
-    hipLaunchKernelGGL(k_srv_reset, dim3(grid), dim3(kWG), 0, s, V, seen, front, next, touched,
-                       ctrl);
+    hipLaunchKernelGGL(k_srv_reset, dim3(grid), dim3(kWG), 0, s, V, sn, front, touched, ctrl);
     return hipGetLastError();
 }
 
-hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, uint64_t* seen, uint64_t mask)
+hipError_t launch_srv_clear(hipStream_t s, int grid, int32_t V, SeenNext* sn, uint64_t mask)
 {
-    hipLaunchKernelGGL(k_srv_clear, dim3(grid), dim3(kWG), 0, s, V, seen, mask);
+    hipLaunchKernelGGL(k_srv_clear, dim3(grid), dim3(kWG), 0, s, V, sn, mask);
     return hipGetLastError();
 }
 
@@ -505,10 +506,10 @@ hipError_t launch_widen16(hipStream_t s, int grid, const int16_t* src, int32_t* 
 }
 
 hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32_t* join,
-                           const int32_t* rank, uint64_t* seen, uint64_t* front,
+                           const int32_t* rank, SeenNext* sn, uint64_t* front,
                            int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl)
 {
-    hipLaunchKernelGGL(k_srv_join, dim3(1), dim3(64), 0, s, V, n_join, join, rank, seen, front,
+    hipLaunchKernelGGL(k_srv_join, dim3(1), dim3(64), 0, s, V, n_join, join, rank, sn, front,
                        lane_out, lane_start, Q, ctrl);
     return hipGetLastError();
 }

@@ -23,7 +23,7 @@ int ok();
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct WsLayout {
     size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, summary;
-    size_t ms_seen, ms_front, ms_next, ms_ctrl, ms_roots, ms_touched;
+    size_t ms_sn, ms_front, ms_ctrl, ms_roots, ms_touched;
     size_t rank, orig, off_r, col_r, hist;
     size_t total;
 };
@@ -58,9 +58,8 @@ struct bfs_graph {
     int32_t* scratch = nullptr;  // small device scratch (create-time checks)
     uint32_t* summary = nullptr; // visited summary: one bit per block of ids
     int32_t summary_shift = 10, summary_blocks = 0, summary_words = 0;
-    uint64_t* ms_seen = nullptr;
+    bfsmi::SeenNext* ms_sn = nullptr;  // seen and next masks, side by side
     uint64_t* ms_front = nullptr;
-    uint64_t* ms_next = nullptr;
     bfsmi::Ctrl* ms_ctrl = nullptr;
     int32_t* ms_roots = nullptr;       // device copy of the batch roots (64)
     uint32_t* ms_touched = nullptr;    // batch: vertices found this level (sparse levels)

@@ -127,7 +127,8 @@ struct SrvQuery {
 // Device state of one running batch, carved from one arena block.
 struct SrvBatch {
     char* mem = nullptr;
-    uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
+    SeenNext* sn = nullptr;  // seen and next masks, side by side
+    uint64_t* front = nullptr;
     uint32_t* touched = nullptr;
     int32_t* q[2] = {nullptr, nullptr};
     int32_t* deg = nullptr;
@@ -186,7 +187,7 @@ static size_t batch_state_bytes(const bfs_graph* g)
     const size_t nblk = (V + kScanChunk - 1) / kScanChunk;
     const size_t ntile = (size_t)((g->nnz + kMinTile - 1) / kMinTile);
     size_t b = 0;
-    b += 4 * align256(V * 8);
+    b += align256(V * 16) + 2 * align256(V * 8);  // seen+next, front, rowstart
     b += align256((V + 31) / 32 * 4);
     b += 4 * align256(V * 4);
     b += align256((V + 1) * 8);
@@ -251,7 +252,7 @@ hipError_t enqueue_srv_level(const bfs_graph* g, SrvBatch* B, hipStream_t s, int
     const int fin = clampi(g->V / 4096, 8, g->num_cus * 4);
     return launch_ms_level(s, scan, expand, fin, ept, g->V, tile_cap, g->s_off, g->s_col, g->orig,
                            B->q[parity], B->q[parity ^ 1], B->deg, B->rowstart, B->suid, B->bsum,
-                           B->cumul, B->tile_k, B->seen, B->front, B->next, B->touched,
+                           B->cumul, B->tile_k, B->sn, B->front, B->touched,
                            B->lane_out, B->lane_start, B->ctrl);
 }
 
@@ -296,9 +297,8 @@ SrvBatch* carve_batch(char* mem, const bfs_graph* g)
         return at;
     };
     const size_t V = (size_t)g->V;
-    B->seen = (uint64_t*)take(V * 8);
+    B->sn = (SeenNext*)take(V * 16);
     B->front = (uint64_t*)take(V * 8);
-    B->next = (uint64_t*)take(V * 8);
     B->touched = (uint32_t*)take((V + 31) / 32 * 4);
     B->q[0] = (int32_t*)take(V * 4);
     B->q[1] = (int32_t*)take(V * 4);
@@ -442,15 +442,15 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
     SrvBatch* B = G.batch;
     bool bad = false;
     if (P.fresh) {
-        bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next,
-                                B->touched, B->ctrl) != hipSuccess;
+        bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->sn, B->front, B->touched,
+                                B->ctrl) != hipSuccess;
         bad |= capture_rounds(g, B, G.stream) != BFS_OK;
     }
     if (P.reset)
-        bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->seen, B->front, B->next,
-                                B->touched, B->ctrl) != hipSuccess;
+        bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->sn, B->front, B->touched,
+                                B->ctrl) != hipSuccess;
     else if (P.clear)
-        bad |= launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->seen, P.clear) != hipSuccess;
+        bad |= launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->sn, P.clear) != hipSuccess;
     for (int i = 0; i < P.n_join; ++i)
         bad |= launch_fill16(G.stream, g->num_cus * 2, P.fill[i], g->V, (int16_t)-1) != hipSuccess;
     if (P.n_join) {
@@ -458,7 +458,7 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
                               hipMemcpyHostToDevice, G.stream) != hipSuccess;
         bad |= hipMemcpyAsync(B->join, G.h_join, (size_t)P.n_join * 2 * sizeof(int32_t),
                               hipMemcpyHostToDevice, G.stream) != hipSuccess;
-        bad |= launch_srv_join(G.stream, g->V, P.n_join, B->join, g->rank, B->seen, B->front,
+        bad |= launch_srv_join(G.stream, g->V, P.n_join, B->join, g->rank, B->sn, B->front,
                                B->lane_out, B->lane_start, B->q[B->parity], B->ctrl) != hipSuccess;
     }
     if (P.release) {
