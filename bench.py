@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-arena-gb", type=int, default=48)
+    ap.add_argument("--serve-arena-gb", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -409,9 +409,22 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
         return
+    def release():
+        # each section starts from an empty device cache (the serving arena
+        # in particular gets fresh, unfragmented memory)
+        import gc
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
     res, g = single_root(args, torch, np, graphgen, bfsmi)
+    g_V, g_nnz = g.V, g.nnz
+    del g
+    release()
     grid = None if args.no_grid else grid_section(args, torch, np, graphgen, bfsmi)
+    release()
     batch = None if args.no_batch else batch_section(args, torch, np, graphgen, bfsmi)
+    release()
     serve = None if args.no_serve else serve_section(args, torch, np, graphgen, bfsmi)
 
     out = {
@@ -429,7 +442,7 @@ def main():
         "data": "synthetic R-MAT (seeded generator, Graph500 parameters), seeded roots",
         "config": {"workload": "rmat%d_single_root" % args.scale, "scale": args.scale,
                    "degree_order": not args.no_degree_order,
-                   "edgefactor": 16, "A": 0.57, "B": 0.19, "C": 0.19, "V": g.V, "nnz": g.nnz,
+                   "edgefactor": 16, "A": 0.57, "B": 0.19, "C": 0.19, "V": g_V, "nnz": g_nnz,
                    "roots": args.roots, "levels_root0": res["levels"],
                    "reached_root0": res["reached"], "edges_scanned_root0": res["edges_scanned"]},
         "roofline": res["roofline"],

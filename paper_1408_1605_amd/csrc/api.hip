@@ -199,11 +199,10 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     }
     g->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     {
-        // the persistent small-level loop needs all its workgroups resident
+        // the persistent small-level loop needs all its workgroups resident:
+        // at most one per CU
         const int per_cu = small_loop_blocks();
-        g->small_grid = prop.cooperativeLaunch && per_cu > 0
-                            ? std::min(kSmallWGs, per_cu * g->num_cus)
-                            : 0;
+        g->small_grid = per_cu > 0 ? std::min(kSmallWGs, g->num_cus) : 0;
     }
 
     // pinned host block: [Ctrl][Ctrl for the batch][64 batch roots]

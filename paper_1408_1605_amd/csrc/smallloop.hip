@@ -3,8 +3,9 @@
 // A level whose frontier holds a few thousand vertices does almost no work,
 // but launching its kernels (degree scan, expansion, bookkeeping) costs a
 // dispatch gap of several microseconds each; a 4096 x 4096 grid has
-// thousands of such levels.  One cooperative kernel of a few dozen
-// workgroups runs them back to back instead:
+// thousands of such levels.  One persistent kernel of a few dozen
+// workgroups (at most one per CU, so all are resident together) runs them
+// back to back instead:
 //   - each workgroup takes an equal slice of the frontier, stages the
 //     slice's degrees, row starts and caller ids in LDS with a prefix sum,
 //     and maps the slice's edges to threads by binary search in it
@@ -313,10 +314,12 @@ hipError_t launch_small_levels(hipStream_t s, int grid, int32_t V, const int64_t
                                int32_t* parent, SmallSync* sy, Ctrl* ctrl, int32_t qlen,
                                int32_t lvl, int32_t qlimit, int64_t rlimit, int32_t dlimit)
 {
-    void* args[] = {&V,     &off,    &col, &orig, &vis,  &vis_old, &Qa,     &Qb,     &level,
-                    &parent, &sy,    &ctrl, &qlen, &lvl, &qlimit,  &rlimit, &dlimit};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_small_levels), dim3(grid),
-                                      dim3(kWG), args, 0, s);
+    // An ordinary launch: the grid (at most one workgroup per CU) is small
+    // enough to be resident at once, and a cooperative launch would make
+    // the runtime stop overlapping later kernels of other streams.
+    hipLaunchKernelGGL(k_small_levels, dim3(grid), dim3(kWG), 0, s, V, off, col, orig, vis, vis_old,
+                       Qa, Qb, level, parent, sy, ctrl, qlen, lvl, qlimit, rlimit, dlimit);
+    return hipGetLastError();
 }
 
 }  // namespace bfsmi
