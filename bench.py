@@ -61,11 +61,13 @@ def cpu_model():
 
 
 def kernel_source_hash():
-    """Hash of the sources that define the expansion kernel; counter-derived
-    traffic is only reported while it matches the hash recorded with it."""
+    """Hash of the sources that define the expansion kernel and the row
+    layout it reads; counter-derived traffic is only reported while it
+    matches the hash recorded with it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("frontier.hip", "tile_map.h", "wave_ops.h", "bfs_internal.h"):
+    for f in ("frontier.hip", "tile_map.h", "wave_ops.h", "bfs_internal.h", "relabel.hip",
+              "rowskip.hip"):
         with open(os.path.join(ROOT, "paper_1408_1605_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

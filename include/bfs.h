@@ -59,18 +59,22 @@ extern "C" {
 #define BFS_WS_BATCH      0x2u /* also reserve the multi-source batch arrays  */
 #define BFS_DEGREE_ORDER  0x4u /* search on a degree-ordered internal copy of
                                   the CSR (built on the GPU at creation, kept
-                                  in the workspace: + 16 V + 4 nnz bytes);
-                                  results are still in the caller's ids     */
+                                  in the workspace: + 56 V + 8 nnz bytes),
+                                  each row grouped by id range with per-row
+                                  counts for the row prefix skip
+                                  (BFS_OPT_ROW_SKIP); results are still in the
+                                  caller's ids                              */
 
 /* Options for bfs_set_option (tuning knobs; defaults are sensible). */
 #define BFS_OPT_EDGES_PER_THREAD 1 /* 1, 2, 4 or 8 frontier edges per thread    */
 #define BFS_OPT_FRONTIER_MODE    2 /* 0 auto (list/bitmap by threshold),
                                       1 list only, 2 bitmap whenever possible */
 #define BFS_OPT_LOOP_DRIVER      3 /* 0 (default) or 2: runs of small levels
-                                      (frontier <= 65536, <= 4M edges) replay
-                                      captured level graphs, one control-block
-                                      read per 8 levels; 1: every level from
-                                      the host, one read per level           */
+                                      (frontier <= 65536 vertices, none of
+                                      degree > 8192) run in one persistent
+                                      launch with a grid barrier per level,
+                                      one control-block read per run; 1: every
+                                      level from the host, one read per level */
 #define BFS_OPT_BATCH_TILE       4 /* edges per workgroup in the batch kernels:
                                       256, 512, 1024 or 2048                  */
 #define BFS_OPT_GRID_WGS         5 /* workgroups per CU for grid-stride kernels */
@@ -82,6 +86,15 @@ extern "C" {
                                       0 off, 1 (default) fully visited id
                                       prefix, 2 prefix + one LDS bit per fully
                                       visited block of ids                    */
+#define BFS_OPT_ROW_SKIP         8 /* degree-ordered graphs: 1 (default) lets a
+                                      heavy level's degree scan drop each
+                                      frontier row's leading block of edges
+                                      into the fully visited id prefix (the
+                                      early visited test of Section 5 applied
+                                      to whole row prefixes: levels and
+                                      parents are unchanged, edges_scanned
+                                      still counts the dropped edges); needs
+                                      BFS_OPT_VISITED_SUMMARY >= 1; 0 off    */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;
@@ -92,14 +105,16 @@ typedef struct bfs_stats {
     int64_t reached;        /* vertices reached (sum of frontier sizes)         */
     int64_t edges_scanned;  /* sum of out-degrees of reached vertices           */
     double  device_ms;      /* stream time of the call (HIP events)             */
-    /* With BFS_OPT_PROFILE: summed stream time of each kernel class. */
+    /* With BFS_OPT_PROFILE: summed stream time of each kernel class
+     * (scan_ms includes the visited summary before heavy levels).        */
     double  init_ms, scan_ms, expand_ms, compact_ms;
     int32_t expand_launches;
     int32_t device_loop_levels; /* levels run inside the device-side loop      */
-    /* Algorithmic bytes of the expansion kernels: per level
-     * 4 * edges (column stream) + 20 * frontier entries (queue entry, its
+    /* Algorithmic bytes of the host-driven expansion kernels: per level
+     * 4 * edges streamed (column ids; edges dropped by the row prefix skip
+     * are not streamed) + 20 * frontier entries (queue entry, its
      * cumulative degree, its row offset) + 4 per discovered vertex for its
-     * parent + 8 per discovered vertex in list mode (queue slot, level).   */
+     * parent + 8 per discovered vertex in list mode (queue slot, level).  */
     int64_t expand_bytes;
 } bfs_stats;
 

@@ -37,6 +37,7 @@ BFS_OPT_BATCH_TILE = 4
 BFS_OPT_GRID_WGS = 5
 BFS_OPT_PROFILE = 6
 BFS_OPT_VISITED_SUMMARY = 7
+BFS_OPT_ROW_SKIP = 8
 
 # Every symbol include/bfs.h declares.
 EXPORTS = (
@@ -315,6 +316,9 @@ class Graph:
 
     def set_option(self, key: int, value: int) -> None:
         bfs_set_option(self.handle, key, value)
+
+    def get_option(self, key: int) -> int:
+        return bfs_get_option(self.handle, key)
 
     def close(self) -> None:
         if self.handle:

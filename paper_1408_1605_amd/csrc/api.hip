@@ -81,6 +81,8 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
         L.off_r = take(((size_t)V + 1) * 8);
         L.col_r = take((size_t)(nnz > 0 ? nnz : 1) * 4);
         L.hist = take(2 * 4096 * 4);
+        L.col_tmp = take((size_t)(nnz > 0 ? nnz : 1) * 4);  // relabelled rows before grouping
+        L.skip = take((size_t)kSkipLevels * V * 4);
     }
     L.total = p;
     return L;
@@ -176,6 +178,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         g->orig = reinterpret_cast<int32_t*>(g->ws + L.orig);
         g->s_off = reinterpret_cast<int64_t*>(g->ws + L.off_r);
         g->s_col = reinterpret_cast<int32_t*>(g->ws + L.col_r);
+        g->skip = reinterpret_cast<int32_t*>(g->ws + L.skip);
     }
     if (flags & BFS_WS_BATCH) {
         g->ms_sn = reinterpret_cast<SeenNext*>(g->ws + L.ms_sn);
@@ -251,10 +254,14 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     g->maxdeg = h[1];
     if (flags & BFS_DEGREE_ORDER) {
         const int64_t tile_cap = (nnz + kMinTile - 1) / kMinTile + 1;
+        int32_t* col_tmp = reinterpret_cast<int32_t*>(g->ws + L.col_tmp);
         e = build_degree_order(s, V, nnz, d_row_offsets, d_col, g->rank, g->orig,
-                               const_cast<int64_t*>(g->s_off), const_cast<int32_t*>(g->s_col),
-                               g->deg, g->rowstart, g->suid, g->bsum, g->tile_k, tile_cap,
+                               const_cast<int64_t*>(g->s_off), col_tmp, g->deg, g->rowstart,
+                               g->suid, g->bsum, g->tile_k, tile_cap,
                                reinterpret_cast<uint32_t*>(g->ws + L.hist), g->ctrl,
+                               g->num_cus * 8);
+        if (e == hipSuccess)
+            e = build_row_skip(s, V, g->s_off, col_tmp, const_cast<int32_t*>(g->s_col), g->skip,
                                g->num_cus * 8);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
@@ -315,6 +322,10 @@ int bfs_set_option(bfs_graph* g, int key, int64_t value)
         if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "visited summary must be 0, 1 or 2");
         g->use_summary = (int)value;
         break;
+    case BFS_OPT_ROW_SKIP:
+        if (value < 0 || value > 1) return fail(BFS_ERR_INVALID, "row skip must be 0 or 1");
+        g->row_skip = (int)value;
+        break;
     default:
         return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
@@ -332,6 +343,7 @@ int bfs_get_option(bfs_graph* g, int key, int64_t* value)
     case BFS_OPT_GRID_WGS: *value = g->grid_wgs; break;
     case BFS_OPT_PROFILE: *value = g->profile; break;
     case BFS_OPT_VISITED_SUMMARY: *value = g->use_summary; break;
+    case BFS_OPT_ROW_SKIP: *value = g->row_skip; break;
     default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
     return ok();
@@ -438,24 +450,26 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         dev_left = false;
         const int32_t* Q = g->q[cur];
         int32_t* Qn = g->q[cur ^ 1];
-        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
-        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
-                                g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
-                                g->ctrl));
         int64_t rmax = (int64_t)qlen * (int64_t)g->maxdeg;
         if (rmax > g->nnz) rmax = g->nnz;
         const int64_t tiles_ub = (rmax + tile - 1) / tile;
         // heavy levels get the visited summary (a cheap pass over the bitmap):
-        // the fully visited prefix always, the LDS block bits in mode 2
+        // the fully visited prefix always, the LDS block bits in mode 2; it
+        // runs before the degree scan so the scan can drop row prefixes
         const bool use_sum = g->use_summary > 0 && rmax > T;
         const bool lds_sum = use_sum && g->use_summary == 2;
+        const bool skip_rows = use_sum && g->skip && g->row_skip;
         const int grid = (int)std::max<int64_t>(
             1, std::min<int64_t>(tiles_ub, lds_sum ? xgrid_sum : xgrid_full));
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
         if (use_sum) {
             const int gs = std::max(1, std::min(grid_cap, (g->summary_blocks + 31) / 32));
             BFS_HIP_TRY(launch_visited_summary(s, gs, g->V, g->W, g->vis, g->summary_shift,
                                                g->summary_blocks, g->summary, g->ctrl));
         }
+        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
+                                g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
+                                g->ctrl, skip_rows ? g->skip : nullptr, g->V));
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
         BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
                                   g->tile_k, g->s_col, g->orig, g->summary, lds_sum ? sum_words : 0,
@@ -483,7 +497,7 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         const int64_t r = g->h_ctrl->r;
         const uint32_t qn = g->h_ctrl->qn_count;
         const bool bm = g->h_ctrl->bitmap_out != 0;
-        edges += r;
+        edges += r + (skip_rows ? g->h_ctrl->skipped : 0);
         xbytes += 4 * r + 20 * (int64_t)qlen + (parents ? 4 : 0) * (int64_t)qn +
                   (bm ? 0 : 8 * (int64_t)qn);
         if (qn == 0) break;

@@ -13,6 +13,8 @@ constexpr int kBitmapWordsPerWG = kWG; // words per workgroup in bitmap->list
 constexpr int kMaxEPT = 8;
 constexpr int kMinTile = kWG;         // smallest edge tile (EPT = 1)
 constexpr int kSummaryMaxWords = 2048; // visited summary: <= 8 KB of LDS
+constexpr int kSkipLow = 16;          // row prefix skip thresholds 2^(16 + i) ...
+constexpr int kSkipLevels = 10;       // ... for i = 0..9
 
 // Per-level control block in device memory.  The host reads it back once
 // per level; the kernels read the fields they need directly.
@@ -40,6 +42,7 @@ struct alignas(64) Ctrl {
     // single-root persistent loop (smallloop.hip)
     int32_t steps;       // levels completed in the loop
     int32_t pad3;
+    int64_t skipped;     // edges the degree scan dropped (row prefix skip)
 };
 
 // ---- single-root kernels (frontier.hip) ----
@@ -50,11 +53,16 @@ hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root,
 
 // Degree scan of the frontier Q: deg, cumul (exclusive, cumul[qlen] = r),
 // rowstart[k] = off[Q[k]], uidv[k] = uid_map ? uid_map[Q[k]] : Q[k], and
-// tile_k (the entry holding each tile's first edge).
+// tile_k (the entry holding each tile's first edge).  With skip (the row
+// prefix skip counts, [kSkipLevels][V]) each entry drops the leading block
+// of its row that points below the largest threshold not above
+// ctrl->full_prefix; deg and rowstart then describe the rest of the row and
+// the dropped edges are added to ctrl->skipped.
 hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int64_t* off,
                        const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
                        int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
-                       int tile, int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl);
+                       int tile, int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl,
+                       const int32_t* skip = nullptr, int32_t V = 0);
 
 // Same scan with the frontier size taken from ctrl->qlen (fixed grid,
 // grid-stride); every kernel returns at once when ctrl->done is set.
@@ -70,8 +78,6 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                          int use_prefix, uint32_t* vis, uint32_t* vis_old, int32_t* level,
                          int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl);
 
-// Visited summary before a heavy level: ctrl->full_prefix and one bit per
-// block of 2^shift ids (set when the whole block is visited).
 // Single-root persistent loop for runs of small levels (smallloop.hip).
 // Zeroed by the host before each launch.
 struct SmallSync {
@@ -88,6 +94,9 @@ hipError_t launch_small_levels(hipStream_t s, int grid, int32_t V, const int64_t
                                int32_t* parent, SmallSync* sy, Ctrl* ctrl, int32_t qlen,
                                int32_t lvl, int32_t qlimit, int64_t rlimit, int32_t dlimit);
 
+// Visited summary before a heavy level: ctrl->full_prefix and one bit per
+// block of 2^shift ids (set when the whole block is visited); clears
+// ctrl->skipped for the level's degree scan.
 hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
                                   const uint32_t* vis, int32_t shift, int32_t nblocks,
                                   uint32_t* summary, Ctrl* ctrl);
@@ -99,10 +108,6 @@ hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
                                   const int32_t* orig, uint32_t* vis, uint32_t* vis_old,
                                   int32_t* Qn, int32_t* level, int32_t lvl, Ctrl* ctrl);
 
-// Degree-ordered internal relabelling (relabel.hip).  rank[v] is v's
-// internal id (vertices in non-increasing degree order, ties arbitrary),
-// orig[rank[v]] = v; off_r / col_r is the CSR in internal ids (row x is
-// the row of orig[x], neighbours mapped through rank).
 // ---- multi-source batch (msbfs.hip) ----
 // The two masks of a vertex that the expansion tests together.
 struct alignas(16) SeenNext {
@@ -139,6 +144,10 @@ hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32
                            const int32_t* rank, SeenNext* sn, uint64_t* front,
                            int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl);
 
+// Degree-ordered internal relabelling (relabel.hip).  rank[v] is v's
+// internal id (vertices in non-increasing degree order, ties arbitrary),
+// orig[rank[v]] = v; off_r / col_r is the CSR in internal ids (row x is
+// the row of orig[x], neighbours mapped through rank).
 hipError_t build_degree_order(hipStream_t s, int32_t V, int64_t nnz, const int64_t* off,
                               const int32_t* col, int32_t* rank, int32_t* orig,
                               int64_t* off_r, int32_t* col_r, int32_t* deg_tmp,
@@ -150,15 +159,10 @@ hipError_t launch_validate_csr(hipStream_t s, int32_t V, int64_t nnz,
                                const int64_t* off, const int32_t* col,
                                int32_t* bad_flag, int32_t* maxdeg, int check_col);
 
-// Device-resident level loop for small frontiers: one cooperative launch
-// that runs levels until the frontier is empty or exceeds small_limit
-// entries / edges.  Returns the HIP status of the launch.
-hipError_t launch_small_loop(hipStream_t s, int grid, const int64_t* off,
-                             const int32_t* col, uint32_t* vis,
-                             uint32_t* vis_old, int32_t* level,
-                             int32_t* parent, int32_t* Qa, int32_t* Qb,
-                             int64_t* cumul, Ctrl* ctrl, int32_t small_limit,
-                             int64_t edge_limit);
-int small_loop_max_grid(int device);
+// Row prefix skip (rowskip.hip): col_out = each row of col_in partitioned
+// by the id ranges cut at 2^(16 + i); skip[i * V + x] = neighbours of row x
+// below 2^(16 + i), i < kSkipLevels.
+hipError_t build_row_skip(hipStream_t s, int32_t V, const int64_t* off, const int32_t* col_in,
+                          int32_t* col_out, int32_t* skip, int grid);
 
 }  // namespace bfsmi

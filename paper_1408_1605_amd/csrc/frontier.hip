@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
         ctrl->levels = 1;
         ctrl->bitmap_levels = 0;
         ctrl->err = 0;
+        ctrl->skipped = 0;
     }
 }
 
@@ -117,22 +118,40 @@ __global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__
                                                      int64_t* __restrict__ rowstart,
                                                      int32_t* __restrict__ uidv,
                                                      int64_t* __restrict__ bsum,
-                                                     const Ctrl* __restrict__ ctrl, int dev)
+                                                     Ctrl* __restrict__ ctrl, int dev,
+                                                     const int32_t* __restrict__ skip, int32_t V)
 {
     __shared__ int64_t s_wave[kWG / 64];
     if (dev && ctrl->done) return;
     const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
     const int64_t nblk = ((int64_t)qlen + kScanChunk - 1) / kScanChunk;
+    // row prefix skip: the largest threshold 2^(16 + i) below which every
+    // id is visited (uniform across the grid: full_prefix is set before)
+    const int32_t* sk = nullptr;
+    if (skip) {
+        const int32_t fp = ctrl->full_prefix;
+        int lv = -1;
+#pragma unroll
+        for (int i = 0; i < kSkipLevels; ++i)
+            if (fp >= (1 << (kSkipLow + i))) lv = i;
+        if (lv >= 0) sk = skip + (int64_t)lv * V;
+    }
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const int64_t base = blk * kScanChunk;
-        int64_t sum = 0;
+        int64_t sum = 0, dropped = 0;
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
             const int64_t k = base + j * kWG + threadIdx.x;
             if (k < qlen) {
                 const int32_t u = Q[k];
-                const int64_t a = off[u];
-                const int64_t d = off[u + 1] - a;
+                int64_t a = off[u];
+                int64_t d = off[u + 1] - a;
+                if (sk) {
+                    const int32_t n = sk[u];
+                    a += n;
+                    d -= n;
+                    dropped += n;
+                }
                 deg[k] = (int32_t)d;
                 rowstart[k] = a;
                 uidv[k] = uid_map ? uid_map[u] : u;
@@ -142,6 +161,12 @@ __global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__
         int64_t tot;
         wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
         if (threadIdx.x == 0) bsum[blk] = tot;
+        if (sk) {
+            int64_t dtot;
+            wg_exclusive_scan<int64_t>(dropped, &dtot, s_wave);
+            if (threadIdx.x == 0 && dtot) atomicAdd((unsigned long long*)&ctrl->skipped,
+                                                    (unsigned long long)dtot);
+        }
     }
 }
 
@@ -179,7 +204,6 @@ __global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, in
         ctrl->qlen = qlen;
         ctrl->bitmap_out = (allow_bitmap == 2 && r > 0) || (allow_bitmap == 1 && r > bitmap_threshold);
         ctrl->qn_count = 0;
-        ctrl->full_prefix = 0x7fffffff;
         ctrl->r_total += r;
         cumul[qlen] = r;
         tile_k[ntiles] = qlen - 1;
@@ -249,12 +273,13 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
 hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int64_t* off,
                        const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
                        int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
-                       int tile, int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl)
+                       int tile, int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl,
+                       const int32_t* skip, int32_t V)
 {
     const int32_t nblk = (int32_t)(((int64_t)qlen + kScanChunk - 1) / kScanChunk);
     if (nblk > 0) {
         hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kWG), 0, s, Q, qlen, off, uid_map, deg,
-                           rowstart, uidv, bsum, ctrl, 0);
+                           rowstart, uidv, bsum, ctrl, 0, skip, V);
     }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, qlen, tile_cap, tile,
                        bitmap_threshold, allow_bitmap, cumul, tile_k, ctrl, 0);
@@ -272,7 +297,7 @@ hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int6
 {
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(kWG), 0, s, Q, 0, off, uid_map, deg,
-                       rowstart, uidv, bsum, ctrl, 1);
+                       rowstart, uidv, bsum, ctrl, 1, (const int32_t*)nullptr, 0);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, 0, tile_cap, tile,
                        (int64_t)1 << 62, 0, cumul, tile_k, ctrl, 1);
     hipLaunchKernelGGL(k_scan_down, dim3(grid), dim3(kWG), 0, s, deg, 0, bsum, tile_cap, tile,
@@ -339,7 +364,10 @@ __global__ __launch_bounds__(kWG) void k_visited_prefix(int32_t V, int32_t W,
                                                         Ctrl* __restrict__ ctrl)
 {
     __shared__ int32_t s_min;
-    if (threadIdx.x == 0) s_min = 0x7fffffff;
+    if (threadIdx.x == 0) {
+        s_min = 0x7fffffff;
+        ctrl->skipped = 0;  // the degree scan that follows adds its dropped edges
+    }
     __syncthreads();
     int32_t first_word = 0x7fffffff;
     for (int32_t i = threadIdx.x; i < nwords; i += kWG)

@@ -24,7 +24,7 @@ int ok();
 struct WsLayout {
     size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, summary;
     size_t ms_sn, ms_front, ms_ctrl, ms_roots, ms_touched;
-    size_t rank, orig, off_r, col_r, hist;
+    size_t rank, orig, off_r, col_r, hist, col_tmp, skip;
     size_t total;
 };
 WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags);
@@ -69,6 +69,7 @@ struct bfs_graph {
     const int32_t* s_col = nullptr;
     int32_t* rank = nullptr;  // caller id -> internal id (degree order only)
     int32_t* orig = nullptr;  // internal id -> caller id (degree order only)
+    int32_t* skip = nullptr;  // row prefix skip counts [kSkipLevels][V] (degree order only)
 
     bfsmi::Ctrl* h_ctrl = nullptr;      // pinned host mirror
     bfsmi::Ctrl* h_ms_ctrl = nullptr;   // pinned host mirror
@@ -89,6 +90,7 @@ struct bfs_graph {
     int grid_wgs = 8;
     int profile = 0;
     int use_summary = 1;
+    int row_skip = 1;
 
     std::atomic<int> busy{0};
 };

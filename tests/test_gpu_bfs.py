@@ -261,3 +261,39 @@ def test_device_loop_hands_back_heavy_level(bfsmi):
         st = check(bfsmi, g, G, int(r))
         assert 0 < st.device_loop_levels < st.levels
     G.close()
+
+
+def test_row_skip_matches_full_rows(bfsmi):
+    # The row prefix skip drops a frontier row's leading edges into the fully
+    # visited id prefix before the expansion: levels, frontier sizes, the edge
+    # count and tree validity must not change, and on R-MAT the expansion
+    # must stream fewer column bytes.
+    g = graphgen.rmat(20)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    assert G.get_option(bfsmi.BFS_OPT_ROW_SKIP) == 1
+    fewer = 0
+    for r in graphgen.pick_roots(g, 3, 55):
+        G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 0)
+        full = check(bfsmi, g, G, int(r))
+        G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 1)
+        for mode in (0, 1, 2):
+            st = check(bfsmi, g, G, int(r), mode=mode)
+            assert st.edges_scanned == full.edges_scanned
+        fewer += st.expand_bytes < full.expand_bytes
+    assert fewer >= 1
+    G.close()
+
+
+@pytest.mark.parametrize("n", [70_000, 300_000, 1_100_000])
+def test_row_skip_whole_rows(bfsmi, n):
+    # star with a leaf as root: the last level's frontier is every other leaf
+    # and each leaf row is one edge back to the visited centre (internal id 0),
+    # so the skip drops whole rows (the level has no edges left to expand);
+    # n spans the thresholds 2^16, 2^18 and 2^20
+    leaves = np.arange(1, n, dtype=np.int64)
+    g = graphgen.from_edges(n, np.zeros(n - 1, np.int64), leaves)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    for r in (1, n - 1, 0):
+        for mode in (0, 1):
+            check(bfsmi, g, G, r, mode=mode)
+    G.close()
