@@ -59,7 +59,7 @@ extern "C" {
 #define BFS_WS_BATCH      0x2u /* also reserve the multi-source batch arrays  */
 #define BFS_DEGREE_ORDER  0x4u /* search on a degree-ordered internal copy of
                                   the CSR (built on the GPU at creation, kept
-                                  in the workspace: + 56 V + 8 nnz bytes),
+                                  in the workspace: + 64 V + 8 nnz bytes),
                                   each row grouped by id range with per-row
                                   counts for the row prefix skip
                                   (BFS_OPT_ROW_SKIP); results are still in the

@@ -83,6 +83,8 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
         L.hist = take(2 * 4096 * 4);
         L.col_tmp = take((size_t)(nnz > 0 ? nnz : 1) * 4);  // relabelled rows before grouping
         L.skip = take((size_t)kSkipLevels * V * 4);
+        L.lvl_int = take((size_t)V * 4);
+        L.par_int = take((size_t)V * 4);
     }
     L.total = p;
     return L;
@@ -179,6 +181,8 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         g->s_off = reinterpret_cast<int64_t*>(g->ws + L.off_r);
         g->s_col = reinterpret_cast<int32_t*>(g->ws + L.col_r);
         g->skip = reinterpret_cast<int32_t*>(g->ws + L.skip);
+        g->lvl_int = reinterpret_cast<int32_t*>(g->ws + L.lvl_int);
+        g->par_int = reinterpret_cast<int32_t*>(g->ws + L.par_int);
     }
     if (flags & BFS_WS_BATCH) {
         g->ms_sn = reinterpret_cast<SeenNext*>(g->ws + L.ms_sn);
@@ -406,8 +410,12 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
     const bool prof = g->profile != 0;
     bfs_stats acc{};
 
+    // under degree order the search writes level / parent by internal id and
+    // k_finish reorders them into the caller's arrays at the end
+    int32_t* lv_s = g->rank ? g->lvl_int : levels;
+    int32_t* pa_s = parents ? (g->rank ? g->par_int : parents) : nullptr;
     BFS_HIP_TRY(hipEventRecord(g->ev0, s));
-    BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, levels, parents, g->vis, g->vis_old,
+    BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, lv_s, pa_s, g->vis, g->vis_old,
                             g->q[0], g->ctrl, grid_cap));
     const int32_t sum_words = g->summary_words;
     const int xgrid_full = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, 0));
@@ -429,8 +437,8 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
             BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
             BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
             BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
-                                            g->vis, g->vis_old, g->q[cur], g->q[cur ^ 1], levels,
-                                            parents, g->small_sync, g->ctrl, qlen, lvl, kSmallQ,
+                                            g->vis, g->vis_old, g->q[cur], g->q[cur ^ 1], lv_s,
+                                            pa_s, g->small_sync, g->ctrl, qlen, lvl, kSmallQ,
                                             (int64_t)g->small_grid * kSmallDeg, kSmallDeg));
             BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
             BFS_HIP_TRY(hipStreamSynchronize(s));
@@ -472,17 +480,17 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
                                 g->ctrl, skip_rows ? g->skip : nullptr, g->V));
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
         BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
-                                  g->tile_k, g->s_col, g->orig, g->summary, lds_sum ? sum_words : 0,
-                                  g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, levels,
-                                  parents, lvl, Qn, g->ctrl));
+                                  g->tile_k, g->s_col, g->summary, lds_sum ? sum_words : 0,
+                                  g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, lv_s,
+                                  pa_s, lvl, Qn, g->ctrl));
         xlaunches++;
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[2], s));
         const bool maybe_bitmap = (allow_bitmap == 2 && rmax > 0) || (allow_bitmap == 1 && rmax > T);
         if (maybe_bitmap) {
             const int64_t nb = ((int64_t)g->W + kBitmapWordsPerWG - 1) / kBitmapWordsPerWG;
             const int grid2 = (int)std::max<int64_t>(1, std::min<int64_t>(nb, grid_cap));
-            BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->orig, g->vis, g->vis_old,
-                                               Qn, levels, lvl, g->ctrl));
+            BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->vis, g->vis_old, Qn, lv_s,
+                                               lvl, g->ctrl));
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
         BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -508,8 +516,16 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         cur ^= 1;
         lvl++;
     }
+    if (g->rank) {
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
+        const int gf = (int)std::max<int64_t>(
+            1, std::min<int64_t>(((int64_t)g->V + kWG - 1) / kWG, grid_cap));
+        BFS_HIP_TRY(launch_finish(s, gf, g->V, g->rank, g->lvl_int, pa_s, levels, parents));
+        if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
+    }
     BFS_HIP_TRY(hipEventRecord(g->ev1, s));
     BFS_HIP_TRY(hipEventSynchronize(g->ev1));
+    if (g->rank && prof) acc.compact_ms += event_ms(g->pev[0], g->pev[3]);
     if (st) {
         *st = acc;
         st->levels = nlevels;

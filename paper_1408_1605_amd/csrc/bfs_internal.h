@@ -71,9 +71,11 @@ hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int6
                            int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
                            int tile, Ctrl* ctrl);
 
+// Expansion of one level (Algorithm 3); level / parent by search id, the
+// level only in list mode (bitmap mode: launch_bitmap_to_queue writes it).
 hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int64_t* rowstart,
                          const int32_t* uidv, const int64_t* cumul, const int32_t* tile_k,
-                         const int32_t* col, const int32_t* orig,
+                         const int32_t* col,
                          const uint32_t* summary, int32_t summary_words, int32_t shift,
                          int use_prefix, uint32_t* vis, uint32_t* vis_old, int32_t* level,
                          int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl);
@@ -104,9 +106,14 @@ hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
 // Resident expansion workgroups per CU for this configuration.
 int expand_blocks_per_cu(int ept, int summary_words);
 
-hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
-                                  const int32_t* orig, uint32_t* vis, uint32_t* vis_old,
-                                  int32_t* Qn, int32_t* level, int32_t lvl, Ctrl* ctrl);
+hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
+                                  uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
+                                  Ctrl* ctrl);
+
+// Degree order: caller-ordered outputs from the internal-id ones.
+hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,
+                         const int32_t* lvl_int, const int32_t* par_int, int32_t* level,
+                         int32_t* parent);
 
 // ---- multi-source batch (msbfs.hip) ----
 // The two masks of a vertex that the expansion tests together.

@@ -21,7 +21,10 @@ namespace bfsmi {
 
 // ---------------------------------------------------------------------------
 // Initialisation (Algorithm 2): level = -1, parent = -1, bitmap = 0, then the
-// root: level 0, parent = root, its visited bit, frontier = {root}.
+// root: level 0, parent = root, its visited bit, frontier = {root}.  level
+// and parent are indexed by search id (the internal id under degree order,
+// where the root's slot is rank[root]); the root's parent value is its
+// caller id.
 
 __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root,
                                               const int32_t* __restrict__ rank,
@@ -34,6 +37,7 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t rin = rank ? rank[root] : root;  // the root's search id
     int64_t done = 0;
     if (vec) {
         // 16-byte stores; both arrays are 16-byte aligned (checked on host)
@@ -44,8 +48,8 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
             int4 lv = make_int4(-1, -1, -1, -1);
             int4 pv = lv;
             const int64_t b = i * 4;
-            if (root >= b && root < b + 4) {
-                const int c = (int)(root - b);
+            if (rin >= b && rin < b + 4) {
+                const int c = (int)(rin - b);
                 if (c == 0) { lv.x = 0; pv.x = root; }
                 if (c == 1) { lv.y = 0; pv.y = root; }
                 if (c == 2) { lv.z = 0; pv.z = root; }
@@ -57,10 +61,9 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
         done = V4 * 4;
     }
     for (int64_t v = done + tid; v < V; v += stride) {
-        level[v] = v == root ? 0 : -1;
-        if (parent) parent[v] = v == root ? root : -1;
+        level[v] = v == rin ? 0 : -1;
+        if (parent) parent[v] = v == rin ? root : -1;
     }
-    const int32_t rin = rank ? rank[root] : root;  // the root's internal id
     const int64_t rw = rin >> 5;
     const uint32_t rb = 1u << (rin & 31);
     for (int64_t i = tid; i < W; i += stride) {
@@ -416,10 +419,11 @@ hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
 // Frontier expansion (Algorithm 3).  Edge slots come from map_tile (the
 // cumulative-degree search of Section 3.4, one search per EPT edges).
 //
-// Vertex ids inside the search may be internal (degree-ordered) ids: then
-// orig maps an internal id to the caller's id for the level / parent
-// outputs.  When summary_words > 0, the visited summary of this level is
-// copied into LDS and answers the early test before any bitmap load.
+// Vertex ids inside the search may be internal (degree-ordered) ids: level
+// and parent are then indexed by internal id (k_finish reorders them) and
+// uidv holds each frontier entry's caller id, the parent value.  When
+// summary_words > 0, the visited summary of this level is copied into LDS
+// and answers the early test before any bitmap load.
 
 template <int EPT>
 __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __restrict__ rowstart,
@@ -427,7 +431,6 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
                                                 const int64_t* __restrict__ cumul,
                                                 const int32_t* __restrict__ tile_k,
                                                 const int32_t* __restrict__ col,
-                                                const int32_t* __restrict__ orig,
                                                 const uint32_t* __restrict__ summary,
                                                 int32_t summary_words, int32_t shift,
                                                 int use_prefix,
@@ -484,14 +487,13 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
         bool win[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) win[j] = need[j] && !(old[j] & (1u << (vv[j] & 31)));
-        int32_t vo[EPT];
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) vo[j] = (win[j] && orig) ? orig[vv[j]] : vv[j];
+        // outputs by search id; in bitmap mode k_bitmap_to_queue writes the
+        // level while it walks the new vertices in id order
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             if (win[j]) {
-                level[vo[j]] = lvl;
-                if (parent) parent[vo[j]] = uu[j];
+                if (list_out) level[vv[j]] = lvl;
+                if (parent) parent[vv[j]] = uu[j];
             }
         }
         if (list_out) {
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
 
 hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int64_t* rowstart,
                          const int32_t* uidv, const int64_t* cumul, const int32_t* tile_k,
-                         const int32_t* col, const int32_t* orig, const uint32_t* summary,
+                         const int32_t* col, const uint32_t* summary,
                          int32_t summary_words, int32_t shift, int use_prefix, uint32_t* vis,
                          uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
                          int32_t* Qn, Ctrl* ctrl)
@@ -536,7 +538,7 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
 #define BFS_EXPAND_CASE(E)                                                                        \
     case E:                                                                                      \
         hipLaunchKernelGGL(k_expand<E>, dim3(grid), dim3(kWG), dyn, s, V, rowstart, uidv, cumul,  \
-                           tile_k, col, orig, summary, summary_words, shift, use_prefix, vis,     \
+                           tile_k, col, summary, summary_words, shift, use_prefix, vis,           \
                            vis_old,                                                              \
                            level, parent,                                                        \
                            lvl, Qn, ctrl);                                                       \
@@ -572,12 +574,11 @@ int expand_blocks_per_cu(int ept, int summary_words)
 // ---------------------------------------------------------------------------
 // Bitmap form of the next frontier: F = vis & ~vis_old (the bits that turned
 // on during this level), vis_old := vis, and F compacted in vertex order to
-// the next queue.  A workgroup handles 256 words (8192 vertices); thread j
-// of pass p looks at vertex p * 256 + j of the block, so level stores and
-// queue stores of a wave are contiguous.
+// the next queue, with level[v] = lvl for each v in F.  A workgroup handles
+// 256 words (8192 vertices); thread j of pass p looks at vertex p * 256 + j
+// of the block, so level stores and queue stores of a wave are contiguous.
 
 __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
-                                                         const int32_t* __restrict__ orig,
                                                          uint32_t* __restrict__ vis,
                                                          uint32_t* __restrict__ vis_old,
                                                          int32_t* __restrict__ Qn,
@@ -618,6 +619,7 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
                     const uint32_t rank = s_off[local >> 5] + (uint32_t)__popc(w & ((1u << bit) - 1u));
                     if (base + rank < (uint32_t)V) Qn[base + rank] = v;
                     else ctrl->err = 3;
+                    level[v] = lvl;
                 }
             }
         }
@@ -625,13 +627,45 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
     }
 }
 
-hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
-                                  const int32_t* orig, uint32_t* vis, uint32_t* vis_old,
-                                  int32_t* Qn, int32_t* level, int32_t lvl, Ctrl* ctrl)
+hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
+                                  uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
+                                  Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid), dim3(kWG), 0, s, V, W, orig, vis, vis_old,
-                       Qn, level, lvl, ctrl);
+    hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid), dim3(kWG), 0, s, V, W, vis, vis_old, Qn,
+                       level, lvl, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Degree order: the search keeps level and parent by internal id (the
+// winners' and the compaction's stores then stay within the search's own id
+// space); one pass at the end writes the caller-ordered outputs,
+// level[c] = lvl_int[rank[c]], parent[c] = par_int[rank[c]].  The stores
+// are coalesced, and the gathers stay local: the relabelling hands each run
+// of 4096 consecutive caller ids one contiguous id range per degree bucket.
+
+__global__ __launch_bounds__(kWG) void k_finish(int32_t V, const int32_t* __restrict__ rank,
+                                                const int32_t* __restrict__ lvl_int,
+                                                const int32_t* __restrict__ par_int,
+                                                int32_t* __restrict__ level,
+                                                int32_t* __restrict__ parent)
+{
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x; c < V; c += stride) {
+        const int32_t x = rank[c];
+        level[c] = lvl_int[x];
+        if (parent) parent[c] = par_int[x];
+    }
+}
+
+hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,
+                         const int32_t* lvl_int, const int32_t* par_int, int32_t* level,
+                         int32_t* parent)
+{
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(kWG), 0, s, V, rank, lvl_int, par_int, level,
+                       parent);
     return hipGetLastError();
 }
 

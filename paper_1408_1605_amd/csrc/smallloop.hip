@@ -232,9 +232,8 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
                     int32_t dv = 0;
                     if (win[j]) {
                         const int32_t v = vv[j];
-                        const int32_t vo = orig ? orig[v] : v;
-                        level[vo] = lvl;
-                        if (parent) parent[vo] = uu[j];
+                        level[v] = lvl;
+                        if (parent) parent[v] = uu[j];
                         dv = (int32_t)(off[v + 1] - off[v]);
                         atomicOr(vis_old + (v >> 5), 1u << (v & 31));
                     }

@@ -58,8 +58,9 @@ def test_workspace_bytes(lib):
     b = lib.bfs_workspace_bytes(1 << 16, 1 << 20, lib.BFS_WS_BATCH)
     c = lib.bfs_workspace_bytes(1 << 16, 1 << 20, lib.BFS_DEGREE_ORDER)
     assert b >= a + 3 * 8 * (1 << 16)
-    # rank, orig, row offsets, two column copies, ten row prefix skip counts
-    assert c >= a + 56 * (1 << 16) + 8 * (1 << 20)
+    # rank, orig, row offsets, two column copies, ten row prefix skip counts,
+    # level and parent by internal id
+    assert c >= a + 64 * (1 << 16) + 8 * (1 << 20)
     assert a % 256 == 0
     # scale 26 stays well inside 288 GB of HBM
     big = lib.bfs_workspace_bytes(1 << 26, 2_110_000_000, lib.BFS_DEGREE_ORDER | lib.BFS_WS_BATCH)
