@@ -416,7 +416,7 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
     int32_t* pa_s = parents ? (g->rank ? g->par_int : parents) : nullptr;
     BFS_HIP_TRY(hipEventRecord(g->ev0, s));
     BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, lv_s, pa_s, g->vis, g->vis_old,
-                            g->q[0], g->ctrl, grid_cap));
+                            g->q[0], g->ctrl, grid_cap, g->rank ? 0 : 1));
     const int32_t sum_words = g->summary_words;
     const int xgrid_full = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, 0));
     const int xgrid_sum = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, sum_words));
@@ -520,7 +520,8 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
         const int gf = (int)std::max<int64_t>(
             1, std::min<int64_t>(((int64_t)g->V + kWG - 1) / kWG, grid_cap));
-        BFS_HIP_TRY(launch_finish(s, gf, g->V, g->rank, g->lvl_int, pa_s, levels, parents));
+        BFS_HIP_TRY(launch_finish(s, gf, g->V, g->rank, g->vis, g->lvl_int, pa_s, levels,
+                                  parents));
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
     }
     BFS_HIP_TRY(hipEventRecord(g->ev1, s));

@@ -46,10 +46,12 @@ struct alignas(64) Ctrl {
 };
 
 // ---- single-root kernels (frontier.hip) ----
+// fill == 0: only the root's level / parent entries (degree order; the
+// finish pass masks unvisited vertices).
 hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root,
                        const int32_t* rank, int32_t* level, int32_t* parent,
                        uint32_t* vis, uint32_t* vis_old, int32_t* Q, Ctrl* ctrl,
-                       int grid_cap);
+                       int grid_cap, int fill);
 
 // Degree scan of the frontier Q: deg, cumul (exclusive, cumul[qlen] = r),
 // rowstart[k] = off[Q[k]], uidv[k] = uid_map ? uid_map[Q[k]] : Q[k], and
@@ -112,8 +114,8 @@ hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
 
 // Degree order: caller-ordered outputs from the internal-id ones.
 hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,
-                         const int32_t* lvl_int, const int32_t* par_int, int32_t* level,
-                         int32_t* parent);
+                         const uint32_t* vis, const int32_t* lvl_int, const int32_t* par_int,
+                         int32_t* level, int32_t* parent);
 
 // ---- multi-source batch (msbfs.hip) ----
 // The two masks of a vertex that the expansion tests together.

@@ -24,7 +24,8 @@ namespace bfsmi {
 // root: level 0, parent = root, its visited bit, frontier = {root}.  level
 // and parent are indexed by search id (the internal id under degree order,
 // where the root's slot is rank[root]); the root's parent value is its
-// caller id.
+// caller id.  With fill == 0 (degree order) only the root's entries are
+// written: k_finish reads level / parent only for visited vertices.
 
 __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root,
                                               const int32_t* __restrict__ rank,
@@ -33,13 +34,17 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
                                               uint32_t* __restrict__ vis,
                                               uint32_t* __restrict__ vis_old,
                                               int32_t* __restrict__ Q, Ctrl* __restrict__ ctrl,
-                                              int vec)
+                                              int vec, int fill)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t rin = rank ? rank[root] : root;  // the root's search id
-    int64_t done = 0;
-    if (vec) {
+    int64_t done = fill ? 0 : V;
+    if (!fill && tid == 0) {
+        level[rin] = 0;
+        if (parent) parent[rin] = root;
+    }
+    if (fill && vec) {
         // 16-byte stores; both arrays are 16-byte aligned (checked on host)
         const int64_t V4 = V / 4;
         int4* l4 = reinterpret_cast<int4*>(level);
@@ -91,17 +96,17 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
 
 hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, const int32_t* rank,
                        int32_t* level, int32_t* parent, uint32_t* vis, uint32_t* vis_old,
-                       int32_t* Q, Ctrl* ctrl, int grid_cap)
+                       int32_t* Q, Ctrl* ctrl, int grid_cap, int fill)
 {
     const bool vec = ((uintptr_t)level % 16 == 0) &&
                      (parent == nullptr || (uintptr_t)parent % 16 == 0);
-    int64_t work = (int64_t)(vec ? V / 4 : V);
+    int64_t work = fill ? (int64_t)(vec ? V / 4 : V) : 0;
     if (W > work) work = W;
     int64_t grid = (work + kWG - 1) / kWG;
     if (grid > grid_cap) grid = grid_cap;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(kWG), 0, s, V, W, root, rank, level,
-                       parent, vis, vis_old, Q, ctrl, vec ? 1 : 0);
+                       parent, vis, vis_old, Q, ctrl, vec ? 1 : 0, fill);
     return hipGetLastError();
 }
 
@@ -493,7 +498,8 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
         for (int j = 0; j < EPT; ++j) {
             if (win[j]) {
                 if (list_out) level[vv[j]] = lvl;
-                if (parent) parent[vv[j]] = uu[j];
+                // written once per search, read back only at its end
+                if (parent) __builtin_nontemporal_store(uu[j], parent + vv[j]);
             }
         }
         if (list_out) {
@@ -640,32 +646,54 @@ hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
 // ---------------------------------------------------------------------------
 // Degree order: the search keeps level and parent by internal id (the
 // winners' and the compaction's stores then stay within the search's own id
-// space); one pass at the end writes the caller-ordered outputs,
-// level[c] = lvl_int[rank[c]], parent[c] = par_int[rank[c]].  The stores
-// are coalesced, and the gathers stay local: the relabelling hands each run
-// of 4096 consecutive caller ids one contiguous id range per degree bucket.
+// space); one pass at the end writes the caller-ordered outputs: for x =
+// rank[c], level[c] = lvl_int[x] and parent[c] = par_int[x] if x is visited,
+// else -1 (the internal arrays are only written for visited vertices).  The
+// stores are coalesced, and the gathers stay local: the relabelling hands
+// each run of 4096 consecutive caller ids one contiguous id range per
+// degree bucket.
+
+// A workgroup takes whole 4096-id chunks (the relabelling's unit), so a
+// chunk's gathers reuse lines in one CU's caches instead of being spread
+// over the XCDs' L2s.
+constexpr int kFinishChunk = 4096;
 
 __global__ __launch_bounds__(kWG) void k_finish(int32_t V, const int32_t* __restrict__ rank,
+                                                const uint32_t* __restrict__ vis,
                                                 const int32_t* __restrict__ lvl_int,
                                                 const int32_t* __restrict__ par_int,
                                                 int32_t* __restrict__ level,
                                                 int32_t* __restrict__ parent)
 {
-    const int64_t stride = (int64_t)gridDim.x * kWG;
-    for (int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x; c < V; c += stride) {
-        const int32_t x = rank[c];
-        level[c] = lvl_int[x];
-        if (parent) parent[c] = par_int[x];
+    const int64_t nchunks = ((int64_t)V + kFinishChunk - 1) / kFinishChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t c0 = ch * kFinishChunk;
+#pragma unroll 4
+        for (int j = 0; j < kFinishChunk / kWG; ++j) {
+            const int64_t c = c0 + j * kWG + threadIdx.x;
+            if (c < V) {
+                const int32_t x = rank[c];
+                int32_t l = -1, p = -1;
+                if ((vis[x >> 5] >> (x & 31)) & 1u) {
+                    l = lvl_int[x];
+                    if (parent) p = par_int[x];
+                }
+                level[c] = l;
+                if (parent) parent[c] = p;
+            }
+        }
     }
 }
 
 hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,
-                         const int32_t* lvl_int, const int32_t* par_int, int32_t* level,
-                         int32_t* parent)
+                         const uint32_t* vis, const int32_t* lvl_int, const int32_t* par_int,
+                         int32_t* level, int32_t* parent)
 {
+    const int64_t nchunks = ((int64_t)V + kFinishChunk - 1) / kFinishChunk;
+    if (grid > nchunks) grid = (int)nchunks;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(kWG), 0, s, V, rank, lvl_int, par_int, level,
-                       parent);
+    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(kWG), 0, s, V, rank, vis, lvl_int, par_int,
+                       level, parent);
     return hipGetLastError();
 }
 
