@@ -1,12 +1,16 @@
 // Degree-ordered internal relabelling, built on the GPU at graph creation.
 //
-// Vertices get internal ids in non-increasing degree order (a counting sort
-// by degree bucket; vertices of degree >= kDegBuckets - 1 share the first
-// bucket, ties in arbitrary order).  The highest-degree vertices then own
-// the lowest ids, so the visited bits that most frontier edges probe sit in
-// a few contiguous words (and the visited summary's fully visited prefix
-// covers them after the first levels).  The relabelled CSR
-// keeps every row's neighbours in the input's order, mapped through rank.
+// Vertices get internal ids in non-increasing order of degree class (a
+// counting sort by class: degrees 0 to 3 on their own, above that four
+// classes per power of two, given by the two bits after the leading one).
+// The highest-degree vertices then own the lowest ids, so the visited bits
+// that most frontier edges probe sit in a few contiguous words (and the
+// visited summary's fully visited prefix covers them after the first
+// levels).  Within a class, each run of 4096 consecutive caller ids gets one
+// contiguous range of internal ids (order inside the run arbitrary), which
+// keeps the end-of-search reordering pass local; the coarse classes keep
+// the number of such ranges per run small.  The relabelled CSR keeps every
+// row's neighbours in the input's order, mapped through rank.
 // Graph creation is not part of a search's timed region (the paper starts
 // its clock after partitioning the graph, Section 4).
 #include "bfs_internal.h"
@@ -15,13 +19,22 @@
 
 namespace bfsmi {
 
-constexpr int kDegBuckets = 4096;
+constexpr int kDegBuckets = 256;
 constexpr int kScatterChunk = kWG * 16;  // vertices per workgroup iteration
 constexpr int kRelabelEPT = 4;
 
+// Bucket 0 holds the highest degree class.
 __device__ __forceinline__ int32_t deg_bucket(int64_t d)
 {
-    return kDegBuckets - 1 - (int32_t)(d < kDegBuckets - 1 ? d : kDegBuckets - 1);
+    int32_t c;
+    if (d < 4) {
+        c = (int32_t)d;
+    } else {
+        const int hb = 63 - __clzll((unsigned long long)d);  // >= 2
+        c = 4 + (hb - 2) * 4 + (int32_t)((d >> (hb - 2)) & 3);
+    }
+    if (c > kDegBuckets - 1) c = kDegBuckets - 1;
+    return kDegBuckets - 1 - c;
 }
 
 __global__ __launch_bounds__(kWG) void k_deg_hist(int32_t V, const int64_t* __restrict__ off,
