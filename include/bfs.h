@@ -188,10 +188,15 @@ int bfs_run_batch(bfs_graph *g, const int32_t *h_roots, int32_t n_roots,
 /* Serving: a resident pool of graphs, queries admitted by an HBM budget and
  * batched per graph into multi-source lanes at level boundaries.          */
 
+/* bfs_server_config.flags */
+#define BFS_SRV_NO_PERSISTENT 0x1u /* deep graphs' rounds use the separate level
+                                      kernels only (no persistent kernel)   */
+
 typedef struct bfs_server_config {
     int32_t max_lanes;       /* lanes per graph batch, 1 .. 64 (default 64)   */
     int32_t max_inflight;    /* graphs with a running batch at once (>= 1)    */
-    int64_t level_budget_us; /* unused by default (0)                         */
+    uint32_t flags;          /* BFS_SRV_* (default 0)                         */
+    uint32_t reserved;       /* 0                                              */
 } bfs_server_config;
 
 typedef struct bfs_timing {
@@ -242,13 +247,14 @@ typedef struct bfs_server_stats {
     uint64_t submitted;    /* queries accepted by bfs_submit                  */
     uint64_t completed;    /* queries finished, failed ones included          */
     uint64_t failed;
-    uint64_t rounds;       /* captured level rounds launched                  */
+    uint64_t rounds;       /* level rounds launched (either kind)             */
     uint64_t levels;       /* levels launched, summed over graph batches      */
     uint64_t lane_levels;  /* sum over launched levels of the live lanes      */
     uint64_t batches;      /* batch states created (arena allocations)        */
     uint64_t joins;        /* queries admitted into a lane                    */
     double   device_ms;    /* device time of all rounds, summed over streams  */
     uint64_t arena_peak;   /* peak arena bytes in use                         */
+    uint64_t persistent_rounds; /* rounds run by the persistent level kernel  */
 } bfs_server_stats;
 
 /* Counters since bfs_server_create (a consistent snapshot). */

@@ -39,6 +39,8 @@ BFS_OPT_PROFILE = 6
 BFS_OPT_VISITED_SUMMARY = 7
 BFS_OPT_ROW_SKIP = 8
 
+BFS_SRV_NO_PERSISTENT = 0x1
+
 # Every symbol include/bfs.h declares.
 EXPORTS = (
     "bfs_last_error", "bfs_version", "bfs_workspace_bytes", "bfs_graph_create",
@@ -65,7 +67,7 @@ class bfs_stats(ctypes.Structure):
 
 class bfs_server_config(ctypes.Structure):
     _fields_ = [("max_lanes", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("level_budget_us", ctypes.c_int64)]
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class bfs_timing(ctypes.Structure):
@@ -79,7 +81,8 @@ class bfs_server_stats(ctypes.Structure):
                 ("failed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
                 ("levels", ctypes.c_uint64), ("lane_levels", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("joins", ctypes.c_uint64),
-                ("device_ms", ctypes.c_double), ("arena_peak", ctypes.c_uint64)]
+                ("device_ms", ctypes.c_double), ("arena_peak", ctypes.c_uint64),
+                ("persistent_rounds", ctypes.c_uint64)]
 
 
 _lib = None
@@ -205,11 +208,11 @@ def bfs_run_batch(g: int, roots, d_levels, stream=None) -> bfs_stats:
 
 
 def bfs_server_create(d_arena, arena_bytes: int | None = None, max_lanes: int = 64,
-                      max_inflight: int = 8) -> int:
+                      max_inflight: int = 8, flags: int = 0) -> int:
     h = ctypes.c_void_p(0)
     if arena_bytes is None:
         arena_bytes = d_arena.numel() * d_arena.element_size()
-    cfg = bfs_server_config(max_lanes, max_inflight, 0)
+    cfg = bfs_server_config(max_lanes, max_inflight, flags, 0)
     _check(load().bfs_server_create(ctypes.byref(h), _ptr(d_arena), arena_bytes,
                                     ctypes.byref(cfg)))
     return int(h.value)

@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbfsmi.so")
 ARCH = os.environ.get("BFSMI_ARCH", "gfx950")
 
-SOURCES = ["frontier.hip", "relabel.hip", "rowskip.hip", "msbfs.hip", "smallloop.hip", "api.hip",
-           "batch_api.hip", "server.cpp"]
+SOURCES = ["frontier.hip", "relabel.hip", "rowskip.hip", "msbfs.hip", "smallloop.hip",
+           "msloop.hip", "api.hip", "batch_api.hip", "server.cpp"]
 
 
 def hipcc() -> str:

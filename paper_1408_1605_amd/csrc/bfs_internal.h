@@ -153,6 +153,29 @@ hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32
                            const int32_t* rank, SeenNext* sn, uint64_t* front,
                            int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl);
 
+// Persistent multi-source levels for serving batches (msloop.hip).  Zeroed
+// by the host before each launch.
+struct MsSync {
+    uint32_t arrive;     // grid barrier: workgroups arrived
+    uint32_t gen;        // grid barrier: generation
+    uint32_t fn[3];      // found-list size, by level mod 3
+    uint32_t qn[3];      // next-frontier size
+    int32_t md[3];       // largest degree in the next frontier
+    int32_t pad;
+    int64_t rn[3];       // edges of the next frontier
+    uint64_t alive[3];   // lanes that found vertices
+};
+int ms_small_loop_blocks();
+// Runs up to max_levels serving levels (OUT16 outputs) from ctrl's state;
+// ctrl->steps = levels run; the frontier ends in Qa; found is int32[V]
+// scratch.
+hipError_t launch_ms_small_levels(hipStream_t s, int grid, int32_t V, const int64_t* off,
+                                  const int32_t* col, const int32_t* orig, SeenNext* sn,
+                                  uint64_t* front, int32_t* Qa, int32_t* Qb, int32_t* found,
+                                  int16_t* const* lane_out, const int32_t* lane_start,
+                                  MsSync* sy, Ctrl* ctrl, int32_t max_levels, int32_t qlimit,
+                                  int64_t rlimit, int32_t dlimit);
+
 // Degree-ordered internal relabelling (relabel.hip).  rank[v] is v's
 // internal id (vertices in non-increasing degree order, ties arbitrary),
 // orig[rank[v]] = v; off_r / col_r is the CSR in internal ids (row x is

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
                     const int b = __builtin_ctzll(m);
                     const int32_t d = lvl - s_start[b];
                     if (d > 32767) ctrl->overflow = 1;
-                    else s_out[b][vo] = (int16_t)d;
+                    else if (s_out[b]) s_out[b][vo] = (int16_t)d;  // null: retired lane
                 }
             } else if (lvl > 127) {
                 ctrl->overflow = 1;

@@ -141,11 +141,15 @@ struct SrvBatch {
     int16_t** lane_out = nullptr;  // device table of 64 result pointers
     int32_t* lane_start = nullptr; // device int32[64]
     int32_t* join = nullptr;       // device int32[128] (root, lane) pairs
+    MsSync* msync = nullptr;       // persistent levels: barrier and counters
     uint64_t lane_ticket[64] = {};
     int64_t lane_age[64] = {};     // levels launched since the lane joined
     uint64_t active = 0;
     int parity = 0;                // stays 0: every replay runs an even number of levels
     bool in_flight = false;
+    bool persist = false;          // the round in flight is the persistent kernel
+    bool big_next = false;         // it stopped before a large level: next round uses the graphs
+    int round_levels = 0;          // levels of the round in flight
     int64_t idle_since = 0;        // steady-clock ns when the batch went idle (0: busy)
     hipGraphExec_t round[3] = {nullptr, nullptr, nullptr};  // 2, 8, 32 levels
 };
@@ -154,6 +158,14 @@ constexpr int kRoundLevels[3] = {2, 8, 32};
 constexpr int64_t kIdleKeepNs = 100 * 1000 * 1000;  // idle batches kept 100 ms
 constexpr double kDeepLife = 48.0;                  // lanes living longer: continuous joins
 constexpr int32_t kSmallV = 1 << 16;                // graphs this small: continuous joins
+// Persistent rounds on deep graphs (msloop.hip): workgroups per launch, at
+// most this many launches in flight (all their workgroups must be resident
+// together), and the level sizes they take.
+constexpr int kMsGrid = 32;
+constexpr int kMaxPersist = 8;
+constexpr int32_t kMsQLimit = 1 << 14;
+constexpr int64_t kMsRLimit = 1 << 16;
+constexpr int32_t kMsDLimit = 8192;
 
 struct SrvGraph {
     bfs_graph* g = nullptr;
@@ -176,8 +188,10 @@ struct StepPlan {
     bool reset = false;      // device error or depth overflow: reset all lanes
     uint64_t clear = 0;      // retired lanes whose seen bits are cleared
     int n_join = 0;          // staged in h_join / h_lane_out
+    bool table = false;      // upload h_lane_out (lanes retired or joined)
     int16_t* fill[64] = {};  // result buffers of the joining lanes
     int round = -1;          // round to replay, -1 none
+    bool persist = false;    // run the round's levels in the persistent kernel
     bool release = false;    // idle too long: give the batch's memory back
 };
 
@@ -194,6 +208,7 @@ static size_t batch_state_bytes(const bfs_graph* g)
     b += align256((nblk + 1) * 8);
     b += align256((ntile + 2) * 4);
     b += align256(sizeof(Ctrl)) + align256(64 * 8) + align256(64 * 4) + align256(128 * 4);
+    b += align256(sizeof(MsSync));
     return b;
 }
 
@@ -216,6 +231,8 @@ struct bfs_server {
     int64_t outstanding = 0;
     std::atomic<bool> stop{false};
     int worker_err = 0;
+    int persist_inflight = 0;         // worker thread only
+    int ms_grid = 0;                  // persistent round workgroups (0: not available)
     bfs_server_stats stats{};
     // result delivery (bfs_poll)
     std::mutex poll_mu;
@@ -312,6 +329,7 @@ SrvBatch* carve_batch(char* mem, const bfs_graph* g)
     B->lane_out = (int16_t**)take(64 * 8);
     B->lane_start = (int32_t*)take(64 * 4);
     B->join = (int32_t*)take(128 * 4);
+    B->msync = (MsSync*)take(sizeof(MsSync));
     return B;
 }
 
@@ -349,7 +367,16 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
     if (round_done) {
         const Ctrl& c = *G.h_ctrl;
         const bool bad = round_err || c.err || c.overflow;
-        const uint64_t retired = bad ? B->active : (B->active & ~c.last_alive);
+        // a persistent round that stopped early without finishing left a large
+        // level, and a round that ended on a frontier above half the
+        // persistent kernel's limit is likely to meet one: the next round runs
+        // the captured level kernels.  A persistent round that ran no level at
+        // all left ctrl (last_alive included) as it was: no lane has ended.
+        B->big_next = !c.done && ((B->persist && c.steps < B->round_levels) ||
+                                  c.qlen > kMsQLimit / 2);
+        const bool no_level = B->persist && c.steps == 0 && !c.done;
+        const uint64_t retired =
+            bad ? B->active : (no_level ? 0ull : (B->active & ~c.last_alive));
         const int64_t t = now_ns();
         for (int b = 0; b < 64; ++b) {
             if (!((retired >> b) & 1ull)) continue;
@@ -375,6 +402,10 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
         if (retired) {
             if (bad) P.reset = true;
             else P.clear = retired;
+            // the device lane table drops the retired lanes' result rows
+            for (int b = 0; b < 64; ++b)
+                if ((retired >> b) & 1ull) G.h_lane_out[b] = nullptr;
+            P.table = true;
             idle_cv.notify_all();
         }
     }
@@ -427,6 +458,8 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
     const int ri = !deep ? 1 : (oldest < 32 ? 0 : (oldest < 256 ? 1 : 2));
     const int K = kRoundLevels[ri];
     P.round = ri;
+    P.persist = deep && ms_grid > 0 && !B->big_next && persist_inflight < kMaxPersist;
+    stats.persistent_rounds += P.persist;
     ++stats.rounds;
     stats.levels += (uint64_t)K;
     stats.lane_levels += (uint64_t)K * (uint64_t)__builtin_popcountll(B->active);
@@ -453,9 +486,10 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
         bad |= launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->sn, P.clear) != hipSuccess;
     for (int i = 0; i < P.n_join; ++i)
         bad |= launch_fill16(G.stream, g->num_cus * 2, P.fill[i], g->V, (int16_t)-1) != hipSuccess;
-    if (P.n_join) {
+    if (P.n_join || P.table)
         bad |= hipMemcpyAsync(B->lane_out, G.h_lane_out, 64 * sizeof(int16_t*),
                               hipMemcpyHostToDevice, G.stream) != hipSuccess;
+    if (P.n_join) {
         bad |= hipMemcpyAsync(B->join, G.h_join, (size_t)P.n_join * 2 * sizeof(int32_t),
                               hipMemcpyHostToDevice, G.stream) != hipSuccess;
         bad |= launch_srv_join(G.stream, g->V, P.n_join, B->join, g->rank, B->sn, B->front,
@@ -471,7 +505,18 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
         G.batch = nullptr;
     } else if (P.round >= 0) {
         bad |= hipEventRecord(G.ev0, G.stream) != hipSuccess;
-        bad |= !B->round[P.round] || hipGraphLaunch(B->round[P.round], G.stream) != hipSuccess;
+        B->persist = P.persist;
+        B->round_levels = kRoundLevels[P.round];
+        if (P.persist) {
+            ++persist_inflight;
+            bad |= hipMemsetAsync(B->msync, 0, sizeof(MsSync), G.stream) != hipSuccess;
+            bad |= launch_ms_small_levels(G.stream, ms_grid, g->V, g->s_off, g->s_col, g->orig,
+                                          B->sn, B->front, B->q[0], B->q[1], B->deg, B->lane_out,
+                                          B->lane_start, B->msync, B->ctrl, B->round_levels,
+                                          kMsQLimit, kMsRLimit, kMsDLimit) != hipSuccess;
+        } else {
+            bad |= !B->round[P.round] || hipGraphLaunch(B->round[P.round], G.stream) != hipSuccess;
+        }
         bad |= hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, G.stream) !=
                hipSuccess;
         bad |= hipEventRecord(G.ev, G.stream) != hipSuccess;
@@ -498,6 +543,7 @@ bool bfs_server::step_graph(SrvGraph& G)
         }
         B->in_flight = false;
         round_done = true;
+        if (B->persist) --persist_inflight;
     }
     StepPlan P;
     {
@@ -549,6 +595,7 @@ int bfs_server_create(bfs_server** out, void* d_arena, size_t arena_bytes,
         c = *cfg;
         if (c.max_lanes < 1 || c.max_lanes > 64) return fail(BFS_ERR_INVALID, "max_lanes must be 1..64");
         if (c.max_inflight < 1) return fail(BFS_ERR_INVALID, "max_inflight must be >= 1");
+        if (c.flags & ~BFS_SRV_NO_PERSISTENT) return fail(BFS_ERR_INVALID, "unknown server flags");
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BFS_ERR_NO_DEVICE, "no HIP device");
@@ -562,6 +609,12 @@ int bfs_server_create(bfs_server** out, void* d_arena, size_t arena_bytes,
     if (!s) return fail(BFS_ERR_INVALID, "out of host memory");
     s->cfg = c;
     s->device = dev;
+    if (!(c.flags & BFS_SRV_NO_PERSISTENT) && ms_small_loop_blocks() > 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+        s->ms_grid = std::min(kMsGrid, cus);
+    }
     // the first 256 bytes of the arena hold the delivery kernel's maximum
     s->d_max = static_cast<int32_t*>(d_arena);
     s->arena.init(static_cast<char*>(d_arena) + 256, arena_bytes - 256);

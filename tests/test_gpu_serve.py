@@ -245,3 +245,51 @@ def test_serve_staggered_arrivals_shallow_and_deep(bfsmi):
     bfsmi.bfs_server_destroy(s)
     for h in handles:
         h.close()
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_serve_persistent_rounds_match_oracle(bfsmi, flags):
+    # deep graphs (lanes living hundreds of levels) run their rounds in the
+    # persistent level kernel unless BFS_SRV_NO_PERSISTENT; an R-MAT graph
+    # beside them keeps the captured rounds.  Queries arrive in waves so
+    # lanes join running batches.
+    graphs = [graphgen.grid(200, 200), graphgen.grid(1000, 3), graphgen.rmat(15, seed=4),
+              graphgen.grid(2, 2), graphgen.grid(400, 400)]
+    handles = [bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER) for g in graphs]
+    nbytes = 512 << 20
+    arena = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = bfsmi.bfs_server_create(arena, max_lanes=64, max_inflight=8, flags=flags)
+    ids = [bfsmi.bfs_server_add_graph(s, h.handle) for h in handles]
+    rng = np.random.default_rng(11 + flags)
+    qs, ts = [], []
+    for wave in range(8):
+        # the 400 x 400 grid gets many lanes: its union frontier outgrows the
+        # persistent kernel's limits, so rounds hand levels back and forth
+        for k in range(16):
+            gi = int(rng.integers(0, len(graphs))) if k < 10 else len(graphs) - 1
+            r = int(rng.integers(0, graphs[gi].V))
+            qs.append((gi, r))
+            ts.append(bfsmi.bfs_submit(s, ids[gi], r))
+        time.sleep(0.004)
+    _say("persistent flags=%d: %d queries submitted" % (flags, len(ts)))
+    drain_completed(bfsmi, s, ts, timeout=120.0)
+    for t, (gi, r) in zip(ts, qs):
+        g = graphs[gi]
+        got = np.empty(g.V, dtype=np.int32)
+        code, tm = bfsmi.bfs_poll(s, t, got)
+        assert code == bfsmi.BFS_OK
+        ref = oracle.bfs(g.off, g.col, r)
+        assert np.array_equal(got, ref.level), (gi, r)
+        assert tm.levels == int(ref.level.max()) + 1
+    st = bfsmi.bfs_server_get_stats(s)
+    _say("persistent flags=%d: rounds %d persistent %d levels %d"
+         % (flags, st.rounds, st.persistent_rounds, st.levels))
+    assert st.completed == len(ts) and st.failed == 0
+    if flags:
+        assert st.persistent_rounds == 0
+    else:
+        assert st.persistent_rounds > 0
+    bfsmi.bfs_server_destroy(s)
+    for h in handles:
+        h.close()
