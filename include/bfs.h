@@ -59,7 +59,8 @@ extern "C" {
 #define BFS_WS_BATCH      0x2u /* also reserve the multi-source batch arrays  */
 #define BFS_DEGREE_ORDER  0x4u /* search on a degree-ordered internal copy of
                                   the CSR (built on the GPU at creation, kept
-                                  in the workspace: + 64 V + 8 nnz bytes),
+                                  in the workspace: + 64 V + 8 nnz bytes,
+                                  + 64 V more with BFS_WS_BATCH),
                                   each row grouped by id range with per-row
                                   counts for the row prefix skip
                                   (BFS_OPT_ROW_SKIP); results are still in the
@@ -128,7 +129,8 @@ int bfs_version(void);
  * Device workspace needed by a graph with V vertices and nnz directed CSR
  * entries.  Pure host arithmetic: never touches the device.
  *   V    : 1 .. 2^31 - 1;  nnz : 0 .. 2^62
- *   flags: BFS_WS_BATCH adds the batch arrays (3 * 8 * V bytes).
+ *   flags: BFS_WS_BATCH adds the batch arrays (3 * 8 * V bytes, and 64 * V
+ *   more with BFS_DEGREE_ORDER: the batch rows by internal id).
  * Errors: BFS_ERR_INVALID for out-of-range sizes or a null bytes pointer.
  */
 int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t *bytes);

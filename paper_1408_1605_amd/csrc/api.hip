@@ -85,6 +85,7 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
         L.skip = take((size_t)kSkipLevels * V * 4);
         L.lvl_int = take((size_t)V * 4);
         L.par_int = take((size_t)V * 4);
+        if (flags & BFS_WS_BATCH) L.ms_out = take((size_t)64 * V);  // batch rows by internal id
     }
     L.total = p;
     return L;
@@ -183,6 +184,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         g->skip = reinterpret_cast<int32_t*>(g->ws + L.skip);
         g->lvl_int = reinterpret_cast<int32_t*>(g->ws + L.lvl_int);
         g->par_int = reinterpret_cast<int32_t*>(g->ws + L.par_int);
+        if (flags & BFS_WS_BATCH) g->ms_out = reinterpret_cast<int8_t*>(g->ws + L.ms_out);
     }
     if (flags & BFS_WS_BATCH) {
         g->ms_sn = reinterpret_cast<SeenNext*>(g->ws + L.ms_sn);

@@ -42,10 +42,12 @@ static BatchGrids batch_grids(bfs_graph* g)
     return b;
 }
 
+// The levels write the int8 rows by search id (no orig): directly the
+// caller's rows without degree order, else g->ms_out, reordered at the end.
 static hipError_t enqueue_level(bfs_graph* g, hipStream_t s, const BatchGrids& b, int parity)
 {
     return launch_ms_level(s, b.scan, b.expand, b.fin, b.ept, g->V, b.tile_cap, g->s_off, g->s_col,
-                           g->orig, g->q[parity], g->q[parity ^ 1], g->deg, g->rowstart, g->suid,
+                           nullptr, g->q[parity], g->q[parity ^ 1], g->deg, g->rowstart, g->suid,
                            g->bsum, g->cumul,
                            g->tile_k, g->ms_sn, g->ms_front, g->ms_touched, nullptr,
                            nullptr, g->ms_ctrl);
@@ -141,8 +143,8 @@ extern "C" int bfs_run_batch(bfs_graph* g, const int32_t* h_roots, int32_t n_roo
     BFS_HIP_TRY(hipMemcpyAsync(g->ms_roots, g->h_roots, sizeof(int32_t) * (size_t)n_roots,
                                hipMemcpyHostToDevice, s));
     BFS_HIP_TRY(launch_ms_init(s, g->num_cus * 8, g->V, g->ms_roots, n_roots, g->rank, g->ms_sn,
-                               g->ms_front, g->ms_touched, d_levels, g->q[0],
-                               g->ms_ctrl));
+                               g->ms_front, g->ms_touched, d_levels, g->rank ? g->ms_out : nullptr,
+                               g->q[0], g->ms_ctrl));
     const bool use_graph = g->loop_driver != 1;
     if (use_graph) {
         rc = capture_batch_graph(g, b);
@@ -164,6 +166,9 @@ extern "C" int bfs_run_batch(bfs_graph* g, const int32_t* h_roots, int32_t n_roo
         if (g->h_ms_ctrl->done) break;
         if (++rounds > max_rounds) return fail(BFS_ERR_HIP, "batch level loop did not terminate");
     }
+    if (g->rank)
+        BFS_HIP_TRY(launch_ms_reorder(s, g->num_cus * 8, g->V, n_roots, g->rank, g->ms_sn,
+                                      g->ms_out, d_levels));
     BFS_HIP_TRY(hipEventRecord(g->ev1, s));
     BFS_HIP_TRY(hipEventSynchronize(g->ev1));
     const Ctrl& c = *g->h_ms_ctrl;

@@ -127,9 +127,16 @@ struct alignas(16) SeenNext {
 // Lanes are bits of a 64-bit mask per vertex: seen (reached), front (this
 // level's frontier), next (found during this level).  All launches read
 // their sizes from ctrl and return at once when ctrl->done is set.
+// out_int non-null: the levels write int8 rows by internal id into out_int
+// (no fill) and launch_ms_reorder produces the caller's rows out8 at the end;
+// else they write out8 directly (filled with -1 here).
 hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* h_roots_dev,
                           int32_t n_roots, const int32_t* rank, SeenNext* sn, uint64_t* front,
-                          uint32_t* touched, int8_t* out8, int32_t* Q, Ctrl* ctrl);
+                          uint32_t* touched, int8_t* out8, int8_t* out_int, int32_t* Q,
+                          Ctrl* ctrl);
+hipError_t launch_ms_reorder(hipStream_t s, int grid, int32_t V, int32_t n_roots,
+                             const int32_t* rank, const SeenNext* sn, const int8_t* out_int,
+                             int8_t* out8);
 hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid,
                            int ept, int32_t V, int64_t tile_cap, const int64_t* off,
                            const int32_t* col, const int32_t* orig, const int32_t* Q,

@@ -53,12 +53,15 @@ __global__ __launch_bounds__(kWG) void k_ms_clear(int32_t V, int32_t n_roots,
     for (int64_t i = done + tid; i < nbytes; i += stride) out8[i] = -1;
 }
 
+// out8: the rows the level kernels write (ctrl->out8): the caller's rows,
+// or with internal_rows the internal-id rows that k_ms_reorder turns into
+// the caller's at the end.
 __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
                                                   const int32_t* __restrict__ roots,
                                                   const int32_t* __restrict__ rank,
                                                   SeenNext* __restrict__ sn,
                                                   uint64_t* __restrict__ front,
-                                                  int8_t* __restrict__ out8,
+                                                  int8_t* __restrict__ out8, int internal_rows,
                                                   int32_t* __restrict__ Q,
                                                   Ctrl* __restrict__ ctrl)
 {
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
     if (b < n_roots) {
         const int32_t r = roots[b];
         s_x[b] = rank ? rank[r] : r;
-        out8[(int64_t)b * V + r] = 0;
+        out8[(int64_t)b * V + (internal_rows ? s_x[b] : r)] = 0;
     }
     __syncthreads();
     if (b < n_roots) {
@@ -111,14 +114,57 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
 
 hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* roots_dev,
                           int32_t n_roots, const int32_t* rank, SeenNext* sn, uint64_t* front,
-                          uint32_t* touched, int8_t* out8, int32_t* Q, Ctrl* ctrl)
+                          uint32_t* touched, int8_t* out8, int8_t* out_int, int32_t* Q,
+                          Ctrl* ctrl)
 {
     if (grid < 1) grid = 1;
+    // internal rows need no fill: the reorder reads only the lanes a vertex has seen
+    int8_t* fill = out_int ? nullptr : out8;
     const int vec = ((uintptr_t)out8 % 16) == 0;
-    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, n_roots, sn, front, touched,
-                       out8, vec);
+    hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kWG), 0, s, V, fill ? n_roots : 0, sn, front,
+                       touched, fill, vec);
     hipLaunchKernelGGL(k_ms_roots, dim3(1), dim3(64), 0, s, V, n_roots, roots_dev, rank, sn, front,
-                       out8, Q, ctrl);
+                       out_int ? out_int : out8, out_int ? 1 : 0, Q, ctrl);
+    return hipGetLastError();
+}
+
+// Batch with degree order: out8[b][c] = out_int[b][rank[c]] where lane b has
+// seen c, else -1.  A workgroup takes runs of 4096 caller ids (the
+// relabelling's unit, one contiguous internal range per degree class), so
+// the gathers reuse lines; for a fixed lane the stores of a wave are
+// contiguous.
+constexpr int kReorderChunk = 4096;
+
+__global__ __launch_bounds__(kWG) void k_ms_reorder(int32_t V, int32_t n_roots,
+                                                    const int32_t* __restrict__ rank,
+                                                    const SeenNext* __restrict__ sn,
+                                                    const int8_t* __restrict__ out_int,
+                                                    int8_t* __restrict__ out8)
+{
+    const int64_t nchunks = ((int64_t)V + kReorderChunk - 1) / kReorderChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        for (int j = 0; j < kReorderChunk / kWG; ++j) {
+            const int64_t c = ch * kReorderChunk + j * kWG + threadIdx.x;
+            if (c >= V) continue;
+            const int32_t x = rank[c];
+            const uint64_t seen = sn[x].seen;
+            for (int b = 0; b < n_roots; ++b) {
+                const int8_t lv = ((seen >> b) & 1ull) ? out_int[(int64_t)b * V + x] : (int8_t)-1;
+                out8[(int64_t)b * V + c] = lv;
+            }
+        }
+    }
+}
+
+hipError_t launch_ms_reorder(hipStream_t s, int grid, int32_t V, int32_t n_roots,
+                             const int32_t* rank, const SeenNext* sn, const int8_t* out_int,
+                             int8_t* out8)
+{
+    const int64_t nchunks = ((int64_t)V + kReorderChunk - 1) / kReorderChunk;
+    if (grid > nchunks) grid = (int)nchunks;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_ms_reorder, dim3(grid), dim3(kWG), 0, s, V, n_roots, rank, sn, out_int,
+                       out8);
     return hipGetLastError();
 }
 
@@ -266,11 +312,23 @@ __global__ __launch_bounds__(kWG) void k_ms_finalize(int32_t V, const int32_t* _
                 }
             } else if (lvl > 127) {
                 ctrl->overflow = 1;
-            } else {
+            } else if (orig) {
                 for (uint64_t m = nw[j]; m; m &= m - 1)
                     out8[(int64_t)__builtin_ctzll(m) * V + vo] = (int8_t)lvl;
             }
             alive |= nw[j];
+        }
+        if (!OUT16 && !orig && lvl <= 127) {
+            // rows by search id: lane b of a wave's vertices is one contiguous
+            // (masked) store, lanes taken in the same order by every thread
+#pragma unroll
+            for (int j = 0; j < IT; ++j) {
+                const int64_t v = c0 + j * kWG + threadIdx.x;
+                for (uint64_t m = wave_or64(nw[j]); m; m &= m - 1) {
+                    const int b = __builtin_ctzll(m);
+                    if ((nw[j] >> b) & 1ull) out8[(int64_t)b * V + v] = (int8_t)lvl;
+                }
+            }
         }
         __syncthreads();  // s_base is rewritten by the next chunk
     }

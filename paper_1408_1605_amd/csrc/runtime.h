@@ -24,7 +24,7 @@ int ok();
 struct WsLayout {
     size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, summary;
     size_t ms_sn, ms_front, ms_ctrl, ms_roots, ms_touched;
-    size_t rank, orig, off_r, col_r, hist, col_tmp, skip, lvl_int, par_int;
+    size_t rank, orig, off_r, col_r, hist, col_tmp, skip, lvl_int, par_int, ms_out;
     size_t total;
 };
 WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags);
@@ -72,6 +72,7 @@ struct bfs_graph {
     int32_t* skip = nullptr;  // row prefix skip counts [kSkipLevels][V] (degree order only)
     int32_t* lvl_int = nullptr;  // level by internal id during a search (degree order only)
     int32_t* par_int = nullptr;  // parent (caller id) by internal id (degree order only)
+    int8_t* ms_out = nullptr;    // batch: int8 rows by internal id (degree order + batch)
 
     bfsmi::Ctrl* h_ctrl = nullptr;      // pinned host mirror
     bfsmi::Ctrl* h_ms_ctrl = nullptr;   // pinned host mirror
