@@ -107,7 +107,9 @@ typedef struct bfs_stats {
     int64_t edges_scanned;  /* sum of out-degrees of reached vertices           */
     double  device_ms;      /* stream time of the call (HIP events)             */
     /* With BFS_OPT_PROFILE: summed stream time of each kernel class
-     * (scan_ms includes the visited summary before heavy levels).        */
+     * (scan_ms includes the visited summary before heavy levels;
+     * compact_ms the bitmap -> queue compaction and, under degree order,
+     * the final pass that writes the caller-ordered outputs).            */
     double  init_ms, scan_ms, expand_ms, compact_ms;
     int32_t expand_launches;
     int32_t device_loop_levels; /* levels run inside the device-side loop      */
