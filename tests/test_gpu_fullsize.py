@@ -46,11 +46,17 @@ def test_rmat26_root_matches_oracle(bfsmi):
     lv, pa, st = G.run(root)
     torch.cuda.synchronize()
     lv, pa = lv.cpu().numpy(), pa.cpu().numpy()
+    # the same search without the row prefix skip
+    G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 0)
+    lv2, _, st2 = G.run(root, want_parents=False)
+    torch.cuda.synchronize()
+    lv2 = lv2.cpu().numpy()
     G.close()
     _say("gpu done: levels %d reached %d" % (st.levels, st.reached))
     ref = oracle.bfs(g.off, g.col, root)
     assert np.array_equal(lv, ref.level)
     assert st.reached == ref.reached and st.edges_scanned == ref.edges_scanned
+    assert np.array_equal(lv2, ref.level) and st2.edges_scanned == ref.edges_scanned
     code, bad = oracle.validate(g.off, g.col, root, lv, pa)
     assert code == 0, (oracle.INVARIANTS[code], bad)
 
