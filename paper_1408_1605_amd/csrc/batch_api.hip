@@ -44,18 +44,23 @@ static BatchGrids batch_grids(bfs_graph* g)
 
 // The levels write the int8 rows by search id (no orig): directly the
 // caller's rows without degree order, else g->ms_out, reordered at the end.
+// With degree order the levels also track the id prefix every searching
+// lane has seen, and each scan drops the rows' blocks below it (the row
+// prefix skip of the single-root search, over the batch's live lanes).
 static hipError_t enqueue_level(bfs_graph* g, hipStream_t s, const BatchGrids& b, int parity)
 {
+    const bool skip = g->skip && g->row_skip;
     return launch_ms_level(s, b.scan, b.expand, b.fin, b.ept, g->V, b.tile_cap, g->s_off, g->s_col,
                            nullptr, g->q[parity], g->q[parity ^ 1], g->deg, g->rowstart, g->suid,
                            g->bsum, g->cumul,
                            g->tile_k, g->ms_sn, g->ms_front, g->ms_touched, nullptr,
-                           nullptr, g->ms_ctrl);
+                           nullptr, g->ms_ctrl, skip ? g->skip : nullptr,
+                           skip ? g->num_cus * 2 : 0);
 }
 
 static int capture_batch_graph(bfs_graph* g, const BatchGrids& b)
 {
-    if (g->ms_graph && g->ms_graph_ept == b.ept) return BFS_OK;
+    if (g->ms_graph && g->ms_graph_ept == b.ept && g->ms_graph_skip == g->row_skip) return BFS_OK;
     if (g->ms_graph) {
         (void)hipGraphExecDestroy(g->ms_graph);
         g->ms_graph = nullptr;
@@ -78,6 +83,7 @@ static int capture_batch_graph(bfs_graph* g, const BatchGrids& b)
         return hip_fail(e, "hipGraphInstantiate");
     }
     g->ms_graph_ept = b.ept;
+    g->ms_graph_skip = g->row_skip;
     return BFS_OK;
 }
 
@@ -177,7 +183,7 @@ extern "C" int bfs_run_batch(bfs_graph* g, const int32_t* h_roots, int32_t n_roo
         std::memset(st, 0, sizeof(*st));
         st->levels = c.levels;
         st->reached = c.reached;
-        st->edges_scanned = c.r_total;
+        st->edges_scanned = c.r_total + c.skipped;  // the skipped edges are part of the union
         st->device_ms = ms_between(g->ev0, g->ev1);
     }
     if (c.overflow) return fail(BFS_ERR_DEPTH, "a batch search is deeper than 127 levels");

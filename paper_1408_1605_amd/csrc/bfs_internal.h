@@ -43,7 +43,10 @@ struct alignas(64) Ctrl {
     int32_t steps;       // levels completed in the loop
     int32_t pad3;
     int64_t skipped;     // edges the degree scan dropped (row prefix skip)
+    int32_t fp_cand;     // batch: first id some live lane has not seen (prefix search)
+    int32_t pad4;
 };
+
 
 // ---- single-root kernels (frontier.hip) ----
 // fill == 0: only the root's level / parent entries (degree order; the
@@ -71,7 +74,7 @@ hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int6
 hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int64_t* off,
                            const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
                            int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
-                           int tile, Ctrl* ctrl);
+                           int tile, Ctrl* ctrl, const int32_t* skip = nullptr, int32_t V = 0);
 
 // Expansion of one level (Algorithm 3); level / parent by search id, the
 // level only in list mode (bitmap mode: launch_bitmap_to_queue writes it).
@@ -137,6 +140,11 @@ hipError_t launch_ms_init(hipStream_t s, int grid, int32_t V, const int32_t* h_r
 hipError_t launch_ms_reorder(hipStream_t s, int grid, int32_t V, int32_t n_roots,
                              const int32_t* rank, const SeenNext* sn, const int8_t* out_int,
                              int8_t* out8);
+// skip non-null (batch on a degree-ordered graph): after each level the
+// longest id prefix that every live lane has seen is found (ctrl->full_prefix)
+// and the next level's scan drops each row's block below the largest cut
+// 2^(16 + i) inside it (the row prefix skip); the dropped edges go to
+// ctrl->skipped.
 hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fin_grid,
                            int ept, int32_t V, int64_t tile_cap, const int64_t* off,
                            const int32_t* col, const int32_t* orig, const int32_t* Q,
@@ -144,7 +152,8 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
                            int64_t* bsum, int64_t* cumul,
                            int32_t* tile_k, SeenNext* sn, uint64_t* front,
                            uint32_t* touched, int16_t* const* lane_out,
-                           const int32_t* lane_start, Ctrl* ctrl);
+                           const int32_t* lane_start, Ctrl* ctrl,
+                           const int32_t* skip = nullptr, int prefix_grid = 0);
 int ms_expand_blocks_per_cu(int ept);
 
 // Serving lanes (msbfs.hip).  lane_out: device table of 64 int16 result

@@ -301,11 +301,11 @@ hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int6
 hipError_t launch_scan_dev(hipStream_t s, int grid, const int32_t* Q, const int64_t* off,
                            const int32_t* uid_map, int32_t* deg, int64_t* rowstart, int32_t* uidv,
                            int64_t* bsum, int64_t* cumul, int32_t* tile_k, int64_t tile_cap,
-                           int tile, Ctrl* ctrl)
+                           int tile, Ctrl* ctrl, const int32_t* skip, int32_t V)
 {
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(kWG), 0, s, Q, 0, off, uid_map, deg,
-                       rowstart, uidv, bsum, ctrl, 1, (const int32_t*)nullptr, 0);
+                       rowstart, uidv, bsum, ctrl, 1, skip, V);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kWG), 0, s, bsum, 0, tile_cap, tile,
                        (int64_t)1 << 62, 0, cumul, tile_k, ctrl, 1);
     hipLaunchKernelGGL(k_scan_down, dim3(grid), dim3(kWG), 0, s, deg, 0, bsum, tile_cap, tile,

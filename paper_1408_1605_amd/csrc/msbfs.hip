@@ -107,6 +107,9 @@ __global__ __launch_bounds__(kWG) void k_ms_roots(int32_t V, int32_t n_roots,
         ctrl->alive = 0;
         ctrl->last_alive = 0;
         ctrl->out8 = out8;
+        ctrl->full_prefix = 0;
+        ctrl->fp_cand = 0x7fffffff;
+        ctrl->skipped = 0;
         ctrl->sparse_limit = V / 64;
         ctrl->sparse = s_n <= V / 64;
     }
@@ -355,9 +358,53 @@ __global__ __launch_bounds__(kWG) void k_ms_clear_front(const int32_t* __restric
     for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < qlen; k += stride) front[Q[k]] = 0;
 }
 
-__global__ void k_ms_advance(Ctrl* __restrict__ ctrl)
+// After a level's finalize: the first id, from the current prefix on, that
+// some lane still searching (found vertices this level) has not seen.  Each
+// workgroup takes 2048-id chunks in order and stops once a smaller candidate
+// is known; k_ms_advance moves ctrl->full_prefix there (the prefix only
+// grows: seen masks grow and the set of searching lanes shrinks).
+constexpr int kPrefixChunk = kWG * 8;
+
+__global__ __launch_bounds__(kWG) void k_ms_prefix(int32_t V, const SeenNext* __restrict__ sn,
+                                                   Ctrl* __restrict__ ctrl)
+{
+    __shared__ int32_t s_min, s_known;
+    if (ctrl->done) return;
+    const uint64_t live = ctrl->alive;
+    if (live == 0) return;  // the batch ends at this level
+    const int32_t p0 = ctrl->full_prefix;
+    for (int64_t c0 = (int64_t)p0 + (int64_t)blockIdx.x * kPrefixChunk; c0 < V;
+         c0 += (int64_t)gridDim.x * kPrefixChunk) {
+        if (threadIdx.x == 0) {
+            s_min = 0x7fffffff;
+            s_known = __hip_atomic_load(&ctrl->fp_cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (c0 >= s_known) break;  // uniform (one read, shared through LDS)
+#pragma unroll
+        for (int j = 0; j < kPrefixChunk / kWG; ++j) {
+            const int64_t x = c0 + j * kWG + threadIdx.x;
+            if (x < V && (sn[x].seen & live) != live) atomicMin(&s_min, (int32_t)x);
+        }
+        __syncthreads();
+        const int32_t m = s_min;
+        if (m != 0x7fffffff) {
+            if (threadIdx.x == 0) atomicMin(&ctrl->fp_cand, m);
+            break;  // uniform
+        }
+        __syncthreads();  // s_min is reset for the next chunk
+    }
+}
+
+__global__ void k_ms_advance(Ctrl* __restrict__ ctrl, int32_t V, int prefix)
 {
     if (ctrl->done) return;
+    if (prefix) {
+        // no candidate: every id from the old prefix on is seen by all live lanes
+        const int32_t c = ctrl->fp_cand;
+        ctrl->full_prefix = c < V ? c : V;
+        ctrl->fp_cand = 0x7fffffff;
+    }
     const uint32_t q = ctrl->qn_count;
     ctrl->sparse = (int32_t)q <= ctrl->sparse_limit;
     ctrl->last_alive = ctrl->alive;  // lanes that found vertices this level
@@ -400,10 +447,12 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
                            const int32_t* orig, const int32_t* Q, int32_t* Qn, int32_t* deg,
                            int64_t* rowstart, int32_t* uidv, int64_t* bsum, int64_t* cumul,
                            int32_t* tile_k, SeenNext* sn, uint64_t* front, uint32_t* touched,
-                           int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl)
+                           int16_t* const* lane_out, const int32_t* lane_start, Ctrl* ctrl,
+                           const int32_t* skip, int prefix_grid)
 {
+    const bool prefix = skip != nullptr && prefix_grid > 0;
     hipError_t e = launch_scan_dev(s, scan_grid, Q, off, nullptr, deg, rowstart, uidv, bsum, cumul,
-                                   tile_k, tile_cap, kWG * ept, ctrl);
+                                   tile_k, tile_cap, kWG * ept, ctrl, prefix ? skip : nullptr, V);
     if (e != hipSuccess) return e;
     if (expand_grid < 1) expand_grid = 1;
     switch (ept) {
@@ -422,7 +471,9 @@ hipError_t launch_ms_level(hipStream_t s, int scan_grid, int expand_grid, int fi
         hipLaunchKernelGGL(k_ms_finalize<false>, dim3(fin_grid), dim3(kWG), 0, s, V, orig, sn,
                            front, touched, Qn, lane_out, lane_start, ctrl);
     }
-    hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ctrl);
+    if (prefix)
+        hipLaunchKernelGGL(k_ms_prefix, dim3(prefix_grid), dim3(kWG), 0, s, V, sn, ctrl);
+    hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ctrl, V, prefix ? 1 : 0);
     return hipGetLastError();
 }
 

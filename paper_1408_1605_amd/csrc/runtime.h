@@ -79,6 +79,7 @@ struct bfs_graph {
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
     hipGraphExec_t ms_graph = nullptr;  // captured batch levels
     int ms_graph_ept = 0;
+    int ms_graph_skip = 0;              // row skip setting the batch levels were captured with
     bfsmi::SmallSync* small_sync = nullptr;  // persistent small-level loop: barrier, counters
     int small_grid = 0;                       // its workgroups (0: not available)
     int32_t* h_roots = nullptr;         // pinned staging for batch roots

@@ -148,3 +148,31 @@ def test_batch_directed(bfsmi):
     for flags in (bfsmi.BFS_WS_BATCH, bfsmi.BFS_WS_BATCH | bfsmi.BFS_DEGREE_ORDER):
         G = bfsmi.Graph.from_csr(g.off, g.col, flags=flags)
         check_batch(bfsmi, g, G, rng.choice(n, 64, replace=False), "directed")
+
+
+def test_batch_row_skip_matches(bfsmi):
+    # the batch's row prefix skip (edges into the id prefix every searching
+    # lane has seen are dropped by the scan) changes neither the rows nor the
+    # union's edge count; roots include vertices of small components, whose
+    # lanes stop early and must not hold the prefix back
+    g = graphgen.rmat(18, seed=12)
+    deg = np.diff(g.off)
+    comp = oracle.components(g.off, g.col)
+    sizes = np.bincount(comp)
+    small = [int(v) for v in np.nonzero((deg > 0) & (sizes[comp] < 50))[0][:4]]
+    assert small, "the graph has no small component"
+    roots = [int(r) for r in graphgen.pick_roots(g, 60, 77)] + small
+    ref = {r: oracle.bfs(g.off, g.col, r) for r in roots}
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER | bfsmi.BFS_WS_BATCH)
+    outs = {}
+    for skip in (1, 0):
+        G.set_option(bfsmi.BFS_OPT_ROW_SKIP, skip)
+        lv, st = G.run_batch(roots)
+        torch.cuda.synchronize()
+        outs[skip] = (lv.cpu().numpy(), st)
+    for k, r in enumerate(roots):
+        want = ref[r].level.astype(np.int8)
+        assert np.array_equal(outs[1][0][k], want), ("skip", k, r)
+        assert np.array_equal(outs[0][0][k], want), ("no skip", k, r)
+    assert outs[1][1].edges_scanned == outs[0][1].edges_scanned
+    G.close()
