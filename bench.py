@@ -349,7 +349,9 @@ def serve_section(args, torch, np, graphgen, bfsmi):
                      "levels_mean": round(float(np.mean([r[5] for r in sub])), 1) if sub else None}
     if st0 is not None:
         d = {f: getattr(st1, f) - getattr(st0, f) for f, _ in st1._fields_}
-        res["server"] = {"rounds": int(d["rounds"]), "levels": int(d["levels"]),
+        res["server"] = {"rounds": int(d["rounds"]),
+                         "persistent_rounds": int(d["persistent_rounds"]),
+                         "levels": int(d["levels"]),
                          "lanes_per_level": round(d["lane_levels"] / max(d["levels"], 1), 2),
                          "batches": int(d["batches"]),
                          "device_ms_per_s": round(d["device_ms"] / max(
