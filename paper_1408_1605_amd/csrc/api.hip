@@ -15,7 +15,7 @@ namespace bfsmi {
 
 constexpr int32_t kSmallQ = 1 << 16;  // frontiers up to this size may run in the persistent loop
 constexpr int32_t kSmallDeg = 8192;   // ... if no frontier vertex has a larger degree
-constexpr int kSmallWGs = 64;         // workgroups of the persistent loop
+constexpr int kSmallWGs = 32;         // workgroups of the persistent loop
 
 
 static thread_local char g_err[512] = "";
@@ -42,6 +42,11 @@ int ok()
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Entries per set of the persistent loop's frontier row data: a frontier
+// that continues in the loop holds at most kSmallQ vertices, and never more
+// than V.
+static int32_t small_side_cap(int32_t V) { return V < kSmallQ ? V : kSmallQ; }
+
 WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
 {
     WsLayout L{};
@@ -67,6 +72,7 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
     L.ctrl = take(sizeof(Ctrl));
     L.scratch = take(256);
     L.sync = take(sizeof(SmallSync));
+    L.sside = take((size_t)small_side_cap(V) * 32);
     L.summary = take(kSummaryMaxWords * 4);
     if (flags & BFS_WS_BATCH) {
         L.ms_sn = take((size_t)V * 16);
@@ -165,6 +171,17 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     g->ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ctrl);
     g->scratch = reinterpret_cast<int32_t*>(g->ws + L.scratch);
     g->small_sync = reinterpret_cast<SmallSync*>(g->ws + L.sync);
+    {
+        const int32_t cap = small_side_cap(V);
+        char* b = g->ws + L.sside;
+        g->small_side.off[0] = reinterpret_cast<int64_t*>(b);
+        g->small_side.off[1] = reinterpret_cast<int64_t*>(b + (size_t)cap * 8);
+        g->small_side.deg[0] = reinterpret_cast<int32_t*>(b + (size_t)cap * 16);
+        g->small_side.deg[1] = reinterpret_cast<int32_t*>(b + (size_t)cap * 20);
+        g->small_side.id[0] = reinterpret_cast<int32_t*>(b + (size_t)cap * 24);
+        g->small_side.id[1] = reinterpret_cast<int32_t*>(b + (size_t)cap * 28);
+        g->small_side.cap = cap;
+    }
     g->summary = reinterpret_cast<uint32_t*>(g->ws + L.summary);
     {
         // blocks of 2^shift ids, at most kSummaryMaxWords * 32 of them
@@ -440,7 +457,8 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
             BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
             BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
                                             g->vis, g->vis_old, g->q[cur], g->q[cur ^ 1], lv_s,
-                                            pa_s, g->small_sync, g->ctrl, qlen, lvl, kSmallQ,
+                                            pa_s, g->small_sync, g->small_side, g->ctrl, qlen,
+                                            lvl, kSmallQ,
                                             (int64_t)g->small_grid * kSmallDeg, kSmallDeg));
             BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
             BFS_HIP_TRY(hipStreamSynchronize(s));

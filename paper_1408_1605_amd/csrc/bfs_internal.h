@@ -87,19 +87,35 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
 
 // Single-root persistent loop for runs of small levels (smallloop.hip).
 // Zeroed by the host before each launch.
+// The grid barrier's counter and the per-level counters sit on separate
+// 128-byte lines, so the barrier's polling does not queue behind the
+// counters' atomics.
 struct SmallSync {
-    uint32_t arrive;   // grid barrier: workgroups arrived
-    uint32_t gen;      // grid barrier: generation
+    uint32_t arrive;   // grid barrier: arrivals (only grows within a launch)
+    uint32_t pad0[31];
     uint32_t qn[3];    // next-frontier size, by level mod 3
+    uint32_t pad1[29];
     int32_t md[3];     // largest degree in the next frontier
+    int32_t pad2[29];
     int64_t rn[3];     // edges of the next frontier
+    int64_t pad3[13];
+};
+// Row start, degree and caller id of each frontier entry, one set per
+// queue (cap entries each), written by the workgroup that claims the vertex
+// so the next level need not look them up.
+struct SmallSide {
+    int64_t* off[2];
+    int32_t* deg[2];
+    int32_t* id[2];
+    int32_t cap;
 };
 int small_loop_blocks();
 hipError_t launch_small_levels(hipStream_t s, int grid, int32_t V, const int64_t* off,
                                const int32_t* col, const int32_t* orig, uint32_t* vis,
                                uint32_t* vis_old, int32_t* Qa, int32_t* Qb, int32_t* level,
-                               int32_t* parent, SmallSync* sy, Ctrl* ctrl, int32_t qlen,
-                               int32_t lvl, int32_t qlimit, int64_t rlimit, int32_t dlimit);
+                               int32_t* parent, SmallSync* sy, SmallSide side, Ctrl* ctrl,
+                               int32_t qlen, int32_t lvl, int32_t qlimit, int64_t rlimit,
+                               int32_t dlimit);
 
 // Visited summary before a heavy level: ctrl->full_prefix and one bit per
 // block of 2^shift ids (set when the whole block is visited); clears
@@ -172,8 +188,8 @@ hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32
 // Persistent multi-source levels for serving batches (msloop.hip).  Zeroed
 // by the host before each launch.
 struct MsSync {
-    uint32_t arrive;     // grid barrier: workgroups arrived
-    uint32_t gen;        // grid barrier: generation
+    uint32_t arrive;     // grid barrier: arrivals (only grows within a launch)
+    uint32_t pad0[31];   // the counters below sit on other lines
     uint32_t fn[3];      // found-list size, by level mod 3
     uint32_t qn[3];      // next-frontier size
     int32_t md[3];       // largest degree in the next frontier

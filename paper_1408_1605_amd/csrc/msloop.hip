@@ -36,31 +36,30 @@ constexpr int kMsEPT = 4;                // edges per thread per pass
 constexpr int kMsTile = kWG * kMsEPT;
 constexpr uint32_t kMsSpinCap = 1u << 24;
 
-__device__ __forceinline__ bool ms_grid_sync(MsSync* sy, uint32_t nwg, uint32_t* s_gen)
+// Grid-wide barrier on a counter that only grows (zeroed before each
+// launch): barrier number k is passed once it reaches k * nwg.  Thread 0 of
+// each workgroup arrives with a release add and waits with relaxed loads
+// followed by an acquire fence.
+__device__ __forceinline__ bool ms_grid_sync(MsSync* sy, uint32_t nwg, uint32_t* s_ep)
 {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
+        const uint32_t target = (*s_ep + 1u) * nwg;
+        uint32_t a = __hip_atomic_fetch_add(&sy->arrive, 1u, __ATOMIC_RELEASE,
+                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
         int ok = 1;
-        const uint32_t g = *s_gen;
-        __threadfence();
-        const uint32_t a = atomicAdd(&sy->arrive, 1u);
-        if (a == nwg - 1) {
-            atomicExch(&sy->arrive, 0u);
-            __threadfence();
-            atomicAdd(&sy->gen, 1u);
-        } else {
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&sy->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kMsSpinCap) {
-                    ok = 0;
-                    break;
-                }
+        uint32_t spins = 0;
+        while ((int32_t)(a - target) < 0) {
+            __builtin_amdgcn_s_sleep(2);
+            a = __hip_atomic_load(&sy->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (++spins > kMsSpinCap) {
+                ok = 0;
+                break;
             }
         }
-        __threadfence();
-        *s_gen = g + 1;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ep += 1u;
         s_ok = ok;
     }
     __syncthreads();
@@ -89,11 +88,11 @@ __global__ __launch_bounds__(kWG) void k_ms_small_levels(
     __shared__ int16_t* s_out[64];
     __shared__ int32_t s_start[64];
     __shared__ uint64_t s_alive[kWG / 64];
-    __shared__ uint32_t s_gen;
+    __shared__ uint32_t s_epoch;
     const uint32_t N = gridDim.x;
     const uint32_t w = blockIdx.x;
     const int t = threadIdx.x;
-    if (t == 0) s_gen = 0;
+    if (t == 0) s_epoch = 0;
     if (t < 64) {
         s_out[t] = lane_out[t];
         s_start[t] = lane_start[t];
@@ -125,7 +124,7 @@ __global__ __launch_bounds__(kWG) void k_ms_small_levels(
             if (mx) atomicMax(&sy->md[2], mx);
         }
     }
-    if (!ms_grid_sync(sy, N, &s_gen)) {
+    if (!ms_grid_sync(sy, N, &s_epoch)) {
         if (t == 0) ctrl->err = 6;
         return;
     }
@@ -263,7 +262,7 @@ __global__ __launch_bounds__(kWG) void k_ms_small_levels(
                 __syncthreads();
             }
         }
-        if (!ms_grid_sync(sy, N, &s_gen)) {
+        if (!ms_grid_sync(sy, N, &s_epoch)) {
             failed = true;
             break;
         }
@@ -326,7 +325,7 @@ __global__ __launch_bounds__(kWG) void k_ms_small_levels(
             if (a) atomicOr(reinterpret_cast<unsigned long long*>(&sy->alive[cs]),
                             (unsigned long long)a);
         }
-        if (!ms_grid_sync(sy, N, &s_gen)) {
+        if (!ms_grid_sync(sy, N, &s_epoch)) {
             failed = true;
             break;
         }

@@ -22,7 +22,7 @@ int ok();
 
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct WsLayout {
-    size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, summary;
+    size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, sside, summary;
     size_t ms_sn, ms_front, ms_ctrl, ms_roots, ms_touched;
     size_t rank, orig, off_r, col_r, hist, col_tmp, skip, lvl_int, par_int, ms_out;
     size_t total;
@@ -81,6 +81,7 @@ struct bfs_graph {
     int ms_graph_ept = 0;
     int ms_graph_skip = 0;              // row skip setting the batch levels were captured with
     bfsmi::SmallSync* small_sync = nullptr;  // persistent small-level loop: barrier, counters
+    bfsmi::SmallSide small_side{};            // ... and its frontier entries' row data
     int small_grid = 0;                       // its workgroups (0: not available)
     int32_t* h_roots = nullptr;         // pinned staging for batch roots
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -10,8 +10,14 @@
 //     slice's degrees, row starts and caller ids in LDS with a prefix sum,
 //     and maps the slice's edges to threads by binary search in it
 //     (Section 3.4, within the slice, so no grid-wide scan is needed);
-//   - claims use the plain-read probe and atomicOr of Algorithm 3; winners
-//     write level and parent and append to the next queue;
+//   - claims go straight to the atomicOr of Algorithm 3 (the plain-read
+//     probe that the heavy levels use would add one dependent memory round
+//     trip per level, and these levels are bound by round trips, not by
+//     atomic throughput); winners write level and parent, and append to the
+//     next queue with one reservation per workgroup and tile;
+//   - a winner also stores its row start, degree and caller id beside its
+//     queue slot, so the next level stages its frontier without looking
+//     them up in the CSR;
 //   - one grid-wide barrier ends each level.
 // The kernel hands the search back to the host when the next frontier, its
 // edge count or its largest degree exceeds the limits the host passes, and
@@ -26,35 +32,32 @@ constexpr int kSmallEPT = 4;
 constexpr int kSmallTile = kWG * kSmallEPT;
 constexpr int kSmallStage = 1024;  // frontier entries staged per pass (4 per thread)
 constexpr uint32_t kSpinCap = 1u << 24;
+static_assert(kWG == 256, "per-wave partials below assume four waves");
 
-// Grid-wide barrier: thread 0 of each workgroup arrives on a counter; the
-// last one resets it and advances the generation the others wait on.
-// Device-scope fences order the level's queue and output writes.
-__device__ __forceinline__ bool grid_sync(SmallSync* sy, uint32_t nwg, uint32_t* s_gen)
+// Grid-wide barrier on a counter that only grows (reset to zero before the
+// launch): barrier number k is passed once it reaches k * nwg.  Thread 0 of
+// each workgroup arrives with a release add and waits with relaxed loads
+// followed by an acquire fence.
+__device__ __forceinline__ bool grid_sync(SmallSync* sy, uint32_t nwg, uint32_t* s_ep)
 {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
+        const uint32_t target = (*s_ep + 1u) * nwg;
+        uint32_t a = __hip_atomic_fetch_add(&sy->arrive, 1u, __ATOMIC_RELEASE,
+                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
         int ok = 1;
-        const uint32_t g = *s_gen;
-        __threadfence();
-        const uint32_t a = atomicAdd(&sy->arrive, 1u);
-        if (a == nwg - 1) {
-            atomicExch(&sy->arrive, 0u);
-            __threadfence();
-            atomicAdd(&sy->gen, 1u);
-        } else {
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&sy->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinCap) {
-                    ok = 0;
-                    break;
-                }
+        uint32_t spins = 0;
+        while ((int32_t)(a - target) < 0) {
+            __builtin_amdgcn_s_sleep(2);
+            a = __hip_atomic_load(&sy->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (++spins > kSpinCap) {
+                ok = 0;
+                break;
             }
         }
-        __threadfence();
-        *s_gen = g + 1;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ep += 1u;
         s_ok = ok;
     }
     __syncthreads();
@@ -65,19 +68,24 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
     int32_t V, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const int32_t* __restrict__ orig, uint32_t* __restrict__ vis, uint32_t* __restrict__ vis_old,
     int32_t* __restrict__ Qa, int32_t* __restrict__ Qb, int32_t* __restrict__ level,
-    int32_t* __restrict__ parent, SmallSync* __restrict__ sy, Ctrl* __restrict__ ctrl,
-    int32_t qlen0, int32_t lvl0, int32_t qlimit, int64_t rlimit, int32_t dlimit)
+    int32_t* __restrict__ parent, SmallSync* __restrict__ sy, SmallSide side,
+    Ctrl* __restrict__ ctrl, int32_t qlen0, int32_t lvl0, int32_t qlimit, int64_t rlimit, int32_t dlimit)
 {
     __shared__ int32_t s_cum[kSmallStage + 1];
     __shared__ int32_t s_uid[kSmallStage];
     __shared__ int64_t s_base[kSmallStage];
     __shared__ uint16_t s_map[kSmallTile];
     __shared__ int32_t s_wave[kWG / 64];
-    __shared__ uint32_t s_gen;
+    __shared__ uint32_t s_wq[kWG / 64];
+    __shared__ int64_t s_rs[kWG / 64];
+    __shared__ int32_t s_rm[kWG / 64];
+    __shared__ uint32_t s_qbase;
+    __shared__ uint32_t s_epoch;
     const uint32_t N = gridDim.x;
     const uint32_t w = blockIdx.x;
     const int t = threadIdx.x;
-    if (t == 0) s_gen = 0;
+    const int wave = t >> 6;
+    if (t == 0) s_epoch = 0;
 
     // The first frontier's size limits are checked before any level runs.
     {
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
             if (mx) atomicMax(&sy->md[2], mx);
         }
     }
-    if (!grid_sync(sy, N, &s_gen)) {
+    if (!grid_sync(sy, N, &s_epoch)) {
         if (t == 0) ctrl->err = 4;
         return;
     }
@@ -127,6 +135,15 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
     while (true) {
         const int32_t* __restrict__ Q = par ? Qb : Qa;
         int32_t* __restrict__ Qn = par ? Qa : Qb;
+        // from the second level on, every frontier entry carries its row start,
+        // degree and caller id, written by the workgroup that claimed it
+        const bool from_side = step > 0;
+        const int64_t* __restrict__ in_off = side.off[par];
+        const int32_t* __restrict__ in_deg = side.deg[par];
+        const int32_t* __restrict__ in_id = side.id[par];
+        int64_t* __restrict__ out_off = side.off[par ^ 1];
+        int32_t* __restrict__ out_deg = side.deg[par ^ 1];
+        int32_t* __restrict__ out_id = side.id[par ^ 1];
         const int cs = step % 3;  // counters of this level
         if (w == 0 && t == 0) {
             // the next level's counters were last read two barriers ago
@@ -135,6 +152,8 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
             sy->rn[nx] = 0;
             sy->md[nx] = 0;
         }
+        int64_t dsum = 0;
+        int32_t dmax = 0;
         const int64_t k0 = (int64_t)qlen * w / N, k1 = (int64_t)qlen * (w + 1) / N;
         for (int64_t s0 = k0; s0 < k1; s0 += kSmallStage) {
             const int32_t n = (int32_t)(k1 - s0 < kSmallStage ? k1 - s0 : kSmallStage);
@@ -149,10 +168,17 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
                 d[m] = 0;
                 id[m] = 0;
                 if (i < n) {
-                    const int32_t u = Q[s0 + i];
-                    a[m] = off[u];
-                    d[m] = (int32_t)(off[u + 1] - a[m]);
-                    id[m] = orig ? orig[u] : u;
+                    if (from_side) {
+                        a[m] = in_off[s0 + i];
+                        d[m] = in_deg[s0 + i];
+                        id[m] = in_id[s0 + i];
+                    } else
+                    {
+                        const int32_t u = Q[s0 + i];
+                        a[m] = off[u];
+                        d[m] = (int32_t)(off[u + 1] - a[m]);
+                        id[m] = orig ? orig[u] : u;
+                    }
                 }
                 tot += d[m];
             }
@@ -203,69 +229,92 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
                     uu[j] = s_uid[i];
                     vv[j] = col[s_base[i] + e0 + sc];
                 }
-                uint32_t wd[kSmallEPT];
-#pragma unroll
-                for (int j = 0; j < kSmallEPT; ++j) wd[j] = ok[j] ? vis[vv[j] >> 5] : ~0u;
-                bool need[kSmallEPT];
                 uint32_t old[kSmallEPT];
 #pragma unroll
                 for (int j = 0; j < kSmallEPT; ++j) {
-                    need[j] = ok[j] && !(wd[j] & (1u << (vv[j] & 31)));
                     old[j] = ~0u;
-                    if (need[j]) old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
+                    if (ok[j]) old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
                 }
-                int64_t dsum = 0;
-                int32_t dmax = 0;
                 bool win[kSmallEPT];
                 uint64_t mask[kSmallEPT];
                 uint32_t total = 0;
 #pragma unroll
                 for (int j = 0; j < kSmallEPT; ++j) {
-                    win[j] = need[j] && !(old[j] & (1u << (vv[j] & 31)));
+                    win[j] = ok[j] && !(old[j] & (1u << (vv[j] & 31)));
                     mask[j] = __ballot(win[j]);
                     total += (uint32_t)__popcll(mask[j]);
                 }
-                uint32_t base = 0;
-                if (total && __lane_id() == 0) base = atomicAdd(&sy->qn[cs], total);
+                int64_t va[kSmallEPT];
+                int32_t vd[kSmallEPT], vi[kSmallEPT];
 #pragma unroll
                 for (int j = 0; j < kSmallEPT; ++j) {
-                    int32_t dv = 0;
+                    va[j] = 0;
+                    vd[j] = 0;
+                    vi[j] = 0;
                     if (win[j]) {
                         const int32_t v = vv[j];
                         level[v] = lvl;
                         if (parent) parent[v] = uu[j];
-                        dv = (int32_t)(off[v + 1] - off[v]);
+                        va[j] = off[v];
+                        vd[j] = (int32_t)(off[v + 1] - va[j]);
+                        vi[j] = orig ? orig[v] : v;
                         atomicOr(vis_old + (v >> 5), 1u << (v & 31));
                     }
-                    dsum += dv;
-                    dmax = dv > dmax ? dv : dmax;
+                    dsum += vd[j];
+                    dmax = vd[j] > dmax ? vd[j] : dmax;
                 }
+                // one queue reservation per workgroup and tile
+                if (__lane_id() == 0) s_wq[wave] = total;
+                __syncthreads();
+                if (t == 0) {
+                    const uint32_t all = s_wq[0] + s_wq[1] + s_wq[2] + s_wq[3];
+                    s_qbase = all ? atomicAdd(&sy->qn[cs], all) : 0u;
+                }
+                __syncthreads();
                 if (total) {
-                    base = __shfl(base, 0, 64);
+                    uint32_t base = s_qbase;
+                    for (int k = 0; k < wave; ++k) base += s_wq[k];
 #pragma unroll
                     for (int j = 0; j < kSmallEPT; ++j) {
                         if (win[j]) {
                             const uint32_t pos = base + lanes_below(mask[j]);
-                            if (pos < (uint32_t)V) Qn[pos] = vv[j];
-                            else ctrl->err = 5;
+                            if (pos < (uint32_t)V) {
+                                Qn[pos] = vv[j];
+                                if (pos < (uint32_t)side.cap) {
+                                    out_off[pos] = va[j];
+                                    out_deg[pos] = vd[j];
+                                    out_id[pos] = vi[j];
+                                }
+                            } else {
+                                ctrl->err = 5;
+                            }
                         }
                         base += (uint32_t)__popcll(mask[j]);
                     }
                 }
-                for (int o = 32; o >= 1; o >>= 1) {
-                    dsum += __shfl_xor(dsum, o, 64);
-                    const int32_t m2 = __shfl_xor(dmax, o, 64);
-                    dmax = m2 > dmax ? m2 : dmax;
-                }
-                if (__lane_id() == 0) {
-                    if (dsum) atomicAdd(reinterpret_cast<unsigned long long*>(&sy->rn[cs]),
-                                        (unsigned long long)dsum);
-                    if (dmax) atomicMax(&sy->md[cs], dmax);
-                }
                 __syncthreads();
             }
         }
-        if (!grid_sync(sy, N, &s_gen)) {
+        // the next frontier's edges and largest degree: one update per workgroup
+        for (int o = 32; o >= 1; o >>= 1) {
+            dsum += __shfl_xor(dsum, o, 64);
+            const int32_t m2 = __shfl_xor(dmax, o, 64);
+            dmax = m2 > dmax ? m2 : dmax;
+        }
+        if (__lane_id() == 0) {
+            s_rs[wave] = dsum;
+            s_rm[wave] = dmax;
+        }
+        __syncthreads();
+        if (t == 0) {
+            const int64_t rs = s_rs[0] + s_rs[1] + s_rs[2] + s_rs[3];
+            int32_t rm = s_rm[0];
+            for (int k = 1; k < kWG / 64; ++k) rm = s_rm[k] > rm ? s_rm[k] : rm;
+            if (rs) atomicAdd(reinterpret_cast<unsigned long long*>(&sy->rn[cs]),
+                              (unsigned long long)rs);
+            if (rm) atomicMax(&sy->md[cs], rm);
+        }
+        if (!grid_sync(sy, N, &s_epoch)) {
             if (t == 0) ctrl->err = 4;
             code = 3;
             break;
@@ -282,7 +331,7 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
         }
         qlen = (int32_t)qn;
         par ^= 1;
-        if ((int32_t)qn > qlimit || rn > rlimit || md > dlimit) {
+        if ((int32_t)qn > qlimit || (int32_t)qn > side.cap || rn > rlimit || md > dlimit) {
             code = 2;
             break;
         }
@@ -310,14 +359,15 @@ int small_loop_blocks()
 hipError_t launch_small_levels(hipStream_t s, int grid, int32_t V, const int64_t* off,
                                const int32_t* col, const int32_t* orig, uint32_t* vis,
                                uint32_t* vis_old, int32_t* Qa, int32_t* Qb, int32_t* level,
-                               int32_t* parent, SmallSync* sy, Ctrl* ctrl, int32_t qlen,
-                               int32_t lvl, int32_t qlimit, int64_t rlimit, int32_t dlimit)
+                               int32_t* parent, SmallSync* sy, SmallSide side, Ctrl* ctrl,
+                               int32_t qlen, int32_t lvl, int32_t qlimit, int64_t rlimit,
+                               int32_t dlimit)
 {
     // An ordinary launch: the grid (at most one workgroup per CU) is small
     // enough to be resident at once, and a cooperative launch would make
     // the runtime stop overlapping later kernels of other streams.
     hipLaunchKernelGGL(k_small_levels, dim3(grid), dim3(kWG), 0, s, V, off, col, orig, vis, vis_old,
-                       Qa, Qb, level, parent, sy, ctrl, qlen, lvl, qlimit, rlimit, dlimit);
+                       Qa, Qb, level, parent, sy, side, ctrl, qlen, lvl, qlimit, rlimit, dlimit);
     return hipGetLastError();
 }
 
