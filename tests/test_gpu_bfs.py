@@ -297,3 +297,39 @@ def test_row_skip_whole_rows(bfsmi, n):
         for mode in (0, 1):
             check(bfsmi, g, G, r, mode=mode)
     G.close()
+
+
+def _fan_tree(fans):
+    """Rooted tree, vertex 0 the root; every vertex of depth d has fans[d]
+    children (ids in breadth-first order)."""
+    src, dst, level_start, width = [], [], 0, 1
+    nxt = 1
+    for f in fans:
+        parents = np.arange(level_start, level_start + width, dtype=np.int64)
+        kids = np.arange(nxt, nxt + width * f, dtype=np.int64)
+        src.append(np.repeat(parents, f))
+        dst.append(kids)
+        level_start, width, nxt = nxt, width * f, nxt + width * f
+    g = graphgen.from_edges(nxt, np.concatenate(src), np.concatenate(dst))
+    g.name = "fan" + "x".join(str(f) for f in fans)
+    return g
+
+
+@pytest.mark.parametrize("fans", [(256, 256), (257, 256), (256, 256, 1), (16, 4096, 1)])
+@pytest.mark.parametrize("dord", [0, 1])
+def test_device_loop_frontier_at_capacity(bfsmi, fans, dord):
+    # The persistent loop keeps each frontier entry's row start, degree and
+    # caller id for at most 65536 entries and hands a larger frontier back to
+    # the host.  (256, 256): a frontier of exactly 65536 leaves continues in
+    # the loop; (257, 256): 65792 leaves go back to the host; the third level
+    # of (256, 256, 1) and (16, 4096, 1) expands a full-capacity frontier
+    # from the carried row data.
+    g = _fan_tree(fans)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER if dord else 0)
+    st = check(bfsmi, g, G, 0)
+    # every expansion runs in the loop, except the one after a frontier
+    # over capacity
+    width = int(np.prod(fans[:2]))
+    assert st.device_loop_levels == (st.levels if width <= 65536 else st.levels - 1)
+    check(bfsmi, g, G, g.V - 1)
+    G.close()
