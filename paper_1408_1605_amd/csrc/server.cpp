@@ -163,8 +163,8 @@ constexpr int32_t kSmallV = 1 << 16;                // graphs this small: contin
 // together), and the level sizes they take.
 constexpr int kMsGrid = 32;
 constexpr int kMaxPersist = 8;
-constexpr int32_t kMsQLimit = 1 << 14;
-constexpr int64_t kMsRLimit = 1 << 16;
+constexpr int32_t kMsQLimit = 1 << 16;
+constexpr int64_t kMsRLimit = 1 << 18;
 constexpr int32_t kMsDLimit = 8192;
 
 struct SrvGraph {
