@@ -351,6 +351,7 @@ def serve_section(args, torch, np, graphgen, bfsmi):
         d = {f: getattr(st1, f) - getattr(st0, f) for f, _ in st1._fields_}
         res["server"] = {"rounds": int(d["rounds"]),
                          "persistent_rounds": int(d["persistent_rounds"]),
+                         "wide_rounds": int(d["wide_rounds"]),
                          "levels": int(d["levels"]),
                          "lanes_per_level": round(d["lane_levels"] / max(d["levels"], 1), 2),
                          "batches": int(d["batches"]),

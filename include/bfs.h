@@ -259,6 +259,9 @@ typedef struct bfs_server_stats {
     double   device_ms;    /* device time of all rounds, summed over streams  */
     uint64_t arena_peak;   /* peak arena bytes in use                         */
     uint64_t persistent_rounds; /* rounds run by the persistent level kernel  */
+    uint64_t wide_rounds;  /* deep-graph rounds given to the captured level
+                              kernels because the union frontier outgrew the
+                              persistent kernel's limits                      */
 } bfs_server_stats;
 
 /* Counters since bfs_server_create (a consistent snapshot). */

@@ -82,7 +82,7 @@ class bfs_server_stats(ctypes.Structure):
                 ("levels", ctypes.c_uint64), ("lane_levels", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("joins", ctypes.c_uint64),
                 ("device_ms", ctypes.c_double), ("arena_peak", ctypes.c_uint64),
-                ("persistent_rounds", ctypes.c_uint64)]
+                ("persistent_rounds", ctypes.c_uint64), ("wide_rounds", ctypes.c_uint64)]
 
 
 _lib = None

@@ -460,6 +460,7 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
     P.round = ri;
     P.persist = deep && ms_grid > 0 && !B->big_next && persist_inflight < kMaxPersist;
     stats.persistent_rounds += P.persist;
+    stats.wide_rounds += deep && ms_grid > 0 && B->big_next;
     ++stats.rounds;
     stats.levels += (uint64_t)K;
     stats.lane_levels += (uint64_t)K * (uint64_t)__builtin_popcountll(B->active);

@@ -264,8 +264,8 @@ def test_serve_persistent_rounds_match_oracle(bfsmi, flags):
     rng = np.random.default_rng(11 + flags)
     qs, ts = [], []
     for wave in range(8):
-        # the 400 x 400 grid gets many lanes: its union frontier outgrows the
-        # persistent kernel's limits, so rounds hand levels back and forth
+        # the 400 x 400 grid gets many lanes at once (wide union frontiers
+        # are covered by test_serve_wide_deep_rounds)
         for k in range(16):
             gi = int(rng.integers(0, len(graphs))) if k < 10 else len(graphs) - 1
             r = int(rng.integers(0, graphs[gi].V))
@@ -293,3 +293,36 @@ def test_serve_persistent_rounds_match_oracle(bfsmi, flags):
     bfsmi.bfs_server_destroy(s)
     for h in handles:
         h.close()
+
+
+def test_serve_wide_deep_rounds(bfsmi):
+    # 48 lanes at once on a 1400 x 1400 grid: the union frontier grows past
+    # what the persistent level kernel takes, so the batch's rounds move to
+    # the captured level kernels and back; every result must still be the
+    # oracle's
+    g = graphgen.grid(1400, 1400)
+    h = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = bfsmi.bfs_server_create(arena, max_lanes=64, max_inflight=4, flags=0)
+    gid = bfsmi.bfs_server_add_graph(s, h.handle)
+    rng = np.random.default_rng(21)
+    # the first two queries teach the server that the graph is deep
+    first = [bfsmi.bfs_submit(s, gid, int(r)) for r in rng.integers(0, g.V, size=2)]
+    drain_completed(bfsmi, s, first, timeout=120.0)
+    roots = [int(r) for r in rng.integers(0, g.V, size=48)]
+    ts = [bfsmi.bfs_submit(s, gid, r) for r in roots]
+    _say("wide deep rounds: %d queries submitted" % len(ts))
+    drain_completed(bfsmi, s, ts, timeout=120.0)
+    for t, r in zip(ts, roots):
+        got = np.empty(g.V, dtype=np.int32)
+        code, tm = bfsmi.bfs_poll(s, t, got)
+        assert code == bfsmi.BFS_OK
+        assert np.array_equal(got, oracle.bfs(g.off, g.col, r).level), r
+    st = bfsmi.bfs_server_get_stats(s)
+    _say("wide deep rounds: rounds %d persistent %d wide %d"
+         % (st.rounds, st.persistent_rounds, st.wide_rounds))
+    assert st.failed == 0
+    assert st.persistent_rounds > 0 and st.wide_rounds > 0
+    bfsmi.bfs_server_destroy(s)
+    h.close()
