@@ -105,7 +105,7 @@ extern "C" {
 
 const char* bfs_last_error(void) { return g_err; }
 
-int bfs_version(void) { return 101; }
+int bfs_version(void) { return 102; }
 
 int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t* bytes)
 {
