@@ -136,3 +136,38 @@ def test_package_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "bfs_oracle" not in text, f
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every ctypes struct of the binding has the C header's field offsets,
+    field sizes and total size (gcc compiles a probe against include/bfs.h)."""
+    import shutil
+    import subprocess
+    from paper_1408_1605_amd import binding
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    structs = [binding.bfs_stats, binding.bfs_server_config, binding.bfs_timing,
+               binding.bfs_server_stats]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bfs.h"', 'int main(void) {']
+    for S in structs:
+        n = S.__name__
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (n, n))
+        for f, _ in S._fields_:
+            lines.append('printf("%s.%s %%zu %%zu\\n", offsetof(%s, %s), sizeof(((%s*)0)->%s));'
+                         % (n, f, n, f, n, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                     text=True).stdout.splitlines())
+    for S in structs:
+        n = S.__name__
+        assert int(got[n]) == ctypes.sizeof(S), n
+        for f, _ in S._fields_:
+            off, size = (int(x) for x in got["%s.%s" % (n, f)].split())
+            desc = getattr(S, f)
+            assert (off, size) == (desc.offset, desc.size), (n, f)
