@@ -4,10 +4,13 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU library and its Python binding
 never import it and share no code with it.
 
-``bfs_oracle.c`` holds a plain serial breadth-first search written from the
-paper's Algorithm 1 at a single processor (R = C = 1) with Algorithm 2's
-initialisation, a union-find connected-components routine, and a validator of
-the BFS-tree invariants.  Everything here is integer arithmetic.
+``bfs_oracle.c`` holds the quantity the paper's search computes (Algorithms 1
+and 2: every reached vertex's level is its hop distance from the root) written
+from its definition as a plain serial first-in first-out traversal, a
+union-find connected-components routine, and a validator of the BFS-tree
+invariants.  ``parallel.py`` runs many roots of the same graph at once in
+forked worker processes (one serial search per worker) and caches results by
+(CSR digest, root).  Everything here is integer arithmetic.
 """
 from __future__ import annotations
 
@@ -28,7 +31,7 @@ INVARIANTS = {
     2: "V2 parent is not a neighbour",
     3: "V3 parent level is not level-1",
     4: "V4 edge spans more than one level / reached-unreached edge",
-    5: "V5 reached set differs from the root's component",
+    5: "V5 reached set differs from the root's component (cross-check)",
     6: "V6 unreached vertex with level/parent set",
 }
 
@@ -58,7 +61,7 @@ def _bind(path: str):
     lib.oracle_components.argtypes = [ctypes.c_int32, i64p, i32p, i32p]
     lib.oracle_validate.restype = ctypes.c_int32
     lib.oracle_validate.argtypes = [ctypes.c_int32, i64p, i32p, ctypes.c_int32, i32p, i32p,
-                                    ctypes.c_int32, ctypes.c_int32, i32p]
+                                    ctypes.c_int32, ctypes.c_int32, i32p, i32p]
     return lib
 
 
@@ -100,7 +103,8 @@ class BFSResult:
 
 
 def bfs(off, col, root: int) -> BFSResult:
-    """Serial level-synchronous BFS from root."""
+    """Hop distances (levels) and one valid parent per vertex from root,
+    by a serial first-in first-out traversal."""
     off, col = _csr(off, col)
     V = off.shape[0] - 1
     if not 0 <= root < V:
@@ -129,22 +133,29 @@ def components(off, col) -> np.ndarray:
 
 
 def validate(off, col, root: int, level, parent, directed: bool = False,
-             rows_sorted: bool = True):
+             rows_sorted: bool = True, comp=None):
     """Check the BFS-tree invariants V1..V6. Returns (code, bad_vertex);
-    code 0 means valid, see INVARIANTS for the others."""
+    code 0 means valid, see INVARIANTS for the others.  comp (the labels
+    from components(), undirected graphs only) adds the V5 cross-check."""
     off, col = _csr(off, col)
     V = off.shape[0] - 1
     level = np.ascontiguousarray(level, dtype=np.int32)
     parent = np.ascontiguousarray(parent, dtype=np.int32)
     if level.shape[0] != V or parent.shape[0] != V:
         raise ValueError("level/parent length must be V")
+    cptr = None
+    if comp is not None:
+        comp = np.ascontiguousarray(comp, dtype=np.int32)
+        if comp.shape[0] != V:
+            raise ValueError("comp length must be V")
+        cptr = _p(comp, ctypes.c_int32)
     bad = ctypes.c_int32(-1)
     code = _load().oracle_validate(V, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32),
                                    int(root), _p(level, ctypes.c_int32),
                                    _p(parent, ctypes.c_int32), int(directed),
-                                   int(rows_sorted), ctypes.byref(bad))
+                                   int(rows_sorted), cptr, ctypes.byref(bad))
     if code < 0:
-        raise MemoryError("oracle_validate failed")
+        raise ValueError("oracle_validate: bad arguments")
     return int(code), int(bad.value)
 
 

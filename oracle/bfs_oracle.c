@@ -5,35 +5,36 @@
  * load this file's library.  The GPU library never links or calls it, and it
  * includes nothing from the GPU library.
  *
- * What is computed.  For a CSR graph and a root r:
- *   level[v]  = number of edges on a shortest path from r to v, or -1 when v
- *               is not reachable (level[r] = 0);
- *   parent[v] = r for v = r, -1 for unreachable v, otherwise the vertex u
- *               through which v was first discovered (an in-neighbour of v
- *               with level[u] = level[v] - 1).
- * This is the output of the paper's search (Algorithm 1 with a single
- * processor, R = C = 1; initialisation as in Algorithm 2): level, pred and
- * the visited bitmap start at -1, -1, 0; the root gets level 0, pred = itself
- * and its visited bit; the current level counter starts at 1; each round
- * scans the edge list of every frontier vertex, and every neighbour whose
- * visited bit is clear is marked visited, given the scanning vertex as
- * predecessor and the current level, and joins the next frontier; the search
- * stops when the next frontier is empty.  Levels are unique; predecessors are
- * one valid choice among several (first discoverer in frontier order, rows
- * scanned in stored order).
+ * What is computed.  For a CSR graph and a root r the search of the paper
+ * (Algorithms 1 and 2, any processor grid) outputs
+ *   level[v]  = the hop distance from r to v along out-edges (the number of
+ *               edges of a shortest path), -1 when v is not reachable;
+ *   parent[v] = r for v = r, -1 for unreachable v, otherwise some u with
+ *               (u, v) an edge and level[u] = level[v] - 1.
+ * level[] has exactly one correct value, so the oracle computes it from its
+ * definition with the textbook first-in first-out traversal: vertices leave
+ * the queue in non-decreasing distance order, and a vertex's distance is
+ * fixed when it is first seen, at one more than the distance of the vertex
+ * being scanned.  parent[] is one valid choice (the vertex that first saw
+ * it); the paper's atomic claim may pick another, so parents elsewhere are
+ * checked with the validator below, never compared.
  *
  * The validator checks a (level, parent) pair against the graph without
- * running a search: it is the tree check described with the benchmark's
- * validation (Section 3.2 states results are validated; the invariants are
- * the standard BFS-tree properties):
+ * running a search: it is the tree check of the benchmark's validation
+ * (Section 3.2 states results are validated; the invariants are the
+ * standard BFS-tree properties):
  *   V1 level[r] = 0 and parent[r] = r;
  *   V2 every reached v != r has parent[v] = u with (u, v) an edge;
  *   V3 ... and level[u] = level[v] - 1;
  *   V4 every edge (u, v): undirected graphs: both ends reached with
  *      |level[u] - level[v]| <= 1, or both unreached; directed graphs:
  *      u reached implies v reached and level[v] <= level[u] + 1;
- *   V5 (undirected) the reached set is exactly r's connected component,
- *      computed by union-find, an algorithm independent of BFS;
+ *   V5 (undirected, optional) the reached set is exactly r's connected
+ *      component as labelled by a caller-supplied comp[] (union-find below,
+ *      an algorithm independent of BFS).  V2 + V3 connect every reached
+ *      vertex to r and V4 closes the reached set under adjacency, so V5
+ *      cannot fail first: it is a cross-check of the others, not a
+ *      separate invariant;
  *   V6 unreached vertices have level -1 and parent -1, and no level is
  *      below -1.
  * V1 + V2/V3 + V4 together force level[] to equal the hop distance.
@@ -43,64 +44,47 @@
 #include <string.h>
 #include <stdio.h>
 
-/* Serial BFS.  frontier_sizes (nullable, capacity V + 1) receives the size
- * of each level's frontier, level 0 first.  Returns the number of levels
- * (number of non-empty frontiers), or -1 on bad arguments / no memory.
+/* Hop distances from root by a first-in first-out traversal.
+ * frontier_sizes (nullable, capacity V + 1) receives the number of vertices
+ * at each distance, 0 first.  Returns the number of distinct distances
+ * (the search's level count), or -1 on bad arguments / no memory.
  * *edges_scanned receives the sum of out-degrees of reached vertices. */
 int32_t oracle_bfs(int32_t V, const int64_t *off, const int32_t *col,
-                   int32_t root, int32_t *level, int32_t *pred,
+                   int32_t root, int32_t *level, int32_t *parent,
                    int64_t *frontier_sizes, int64_t *edges_scanned)
 {
-    if (V <= 0 || root < 0 || root >= V || !off || !level || !pred) return -1;
-    uint8_t *bmap = (uint8_t *)calloc((size_t)V, 1);
-    int32_t *front = (int32_t *)malloc((size_t)V * sizeof(int32_t));
-    int32_t *next = (int32_t *)malloc((size_t)V * sizeof(int32_t));
-    if (!bmap || !front || !next) {
-        free(bmap);
-        free(front);
-        free(next);
-        return -1;
-    }
-    for (int32_t v = 0; v < V; ++v) {
-        level[v] = -1;
-        pred[v] = -1;
-    }
-    int64_t nfront = 0, scanned = 0;
+    if (V <= 0 || root < 0 || root >= V || !off || !level || !parent) return -1;
+    int32_t *fifo = (int32_t *)malloc((size_t)V * sizeof(int32_t));
+    if (!fifo) return -1;
+    memset(level, 0xff, (size_t)V * sizeof(int32_t));   /* all -1 */
+    memset(parent, 0xff, (size_t)V * sizeof(int32_t));
     level[root] = 0;
-    pred[root] = root;
-    bmap[root] = 1;
-    front[nfront++] = root;
-    int32_t nlevels = 0;
-    int32_t lvl = 1;
-    while (1) {
-        if (frontier_sizes) frontier_sizes[nlevels] = nfront;
-        nlevels++;
-        int64_t nnext = 0;
-        for (int64_t i = 0; i < nfront; ++i) {
-            const int32_t u = front[i];
-            scanned += off[u + 1] - off[u];
-            for (int64_t e = off[u]; e < off[u + 1]; ++e) {
-                const int32_t v = col[e];
-                if (bmap[v] == 0) {
-                    bmap[v] = 1;
-                    pred[v] = u;
-                    level[v] = lvl;
-                    next[nnext++] = v;
-                }
+    parent[root] = root;
+    int64_t head = 0, tail = 0, degsum = 0;
+    fifo[tail++] = root;
+    while (head < tail) {
+        const int32_t x = fifo[head++];
+        const int32_t dx = level[x];
+        const int64_t a = off[x], b = off[x + 1];
+        degsum += b - a;
+        for (int64_t e = a; e < b; ++e) {
+            const int32_t y = col[e];
+            if (level[y] < 0) {
+                level[y] = dx + 1;
+                parent[y] = x;
+                fifo[tail++] = y;
             }
         }
-        if (nnext == 0) break;
-        int32_t *t = front;
-        front = next;
-        next = t;
-        nfront = nnext;
-        lvl++;
     }
-    if (edges_scanned) *edges_scanned = scanned;
-    free(bmap);
-    free(front);
-    free(next);
-    return nlevels;
+    /* the queue holds every reached vertex once, in distance order */
+    const int32_t depth = level[fifo[tail - 1]];
+    if (frontier_sizes) {
+        for (int32_t d = 0; d <= depth; ++d) frontier_sizes[d] = 0;
+        for (int64_t i = 0; i < tail; ++i) frontier_sizes[level[fifo[i]]]++;
+    }
+    if (edges_scanned) *edges_scanned = degsum;
+    free(fifo);
+    return depth + 1;
 }
 
 /* Union-find with path halving and union by size. */
@@ -176,12 +160,14 @@ static int has_edge(const int64_t *off, const int32_t *col, int32_t u, int32_t x
  * Validate a BFS result.  Returns 0 when every invariant holds, otherwise the
  * number (1..6) of the first failing invariant, with *bad_vertex set to an
  * offending vertex.  directed = 0 assumes a symmetric graph.  rows_sorted
- * allows binary search for edge membership.  -1 on no memory / bad args.
+ * allows binary search for edge membership.  comp (nullable, undirected
+ * only) enables V5 against those component labels.  -1 on bad args.
  */
 int32_t oracle_validate(int32_t V, const int64_t *off, const int32_t *col,
                         int32_t root, const int32_t *level,
                         const int32_t *parent, int32_t directed,
-                        int32_t rows_sorted, int32_t *bad_vertex)
+                        int32_t rows_sorted, const int32_t *comp,
+                        int32_t *bad_vertex)
 {
     int32_t dummy;
     if (!bad_vertex) bad_vertex = &dummy;
@@ -242,22 +228,14 @@ int32_t oracle_validate(int32_t V, const int64_t *off, const int32_t *col,
         }
     }
     /* V5 */
-    if (!directed) {
-        int32_t *comp = (int32_t *)malloc((size_t)V * sizeof(int32_t));
-        if (!comp) return -1;
-        if (oracle_components(V, off, col, comp) != 0) {
-            free(comp);
-            return -1;
-        }
+    if (!directed && comp) {
         const int32_t rc = comp[root];
         for (int32_t v = 0; v < V; ++v) {
             if ((comp[v] == rc) != (level[v] >= 0)) {
                 *bad_vertex = v;
-                free(comp);
                 return 5;
             }
         }
-        free(comp);
     }
     return 0;
 }

@@ -1,6 +1,7 @@
 """Plants plausible mistakes in a copy of the CPU oracle (on the CPU) and
 checks that the pins catch each one: a dropped edge, an off-by-one level, a
-wrong index, a missing visited test, a wrong parent, a weakened validator.
+wrong index, a missing visited test, a wrong parent, a stack instead of a
+queue, a wrong per-level count, a weakened validator.
 """
 import multiprocessing
 import os
@@ -18,16 +19,16 @@ import oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "bfs_oracle.c")
 
 BFS_MUTANTS = {
-    "level_starts_at_0": ("int32_t lvl = 1;", "int32_t lvl = 0;"),
-    "level_never_advances": ("        lvl++;\n", "\n"),
-    "drops_last_edge": ("for (int64_t e = off[u]; e < off[u + 1]; ++e) {\n                const int32_t v",
-                        "for (int64_t e = off[u]; e < off[u + 1] - 1; ++e) {\n                const int32_t v"),
-    "wrong_neighbour_index": ("const int32_t v = col[e];\n                if (bmap",
-                              "const int32_t v = col[e > off[u] ? e - 1 : e];\n                if (bmap"),
-    "no_visited_test": ("if (bmap[v] == 0) {", "if (bmap[v] <= 1) {"),
-    "parent_is_self": ("pred[v] = u;", "pred[v] = v;"),
-    "root_not_marked": ("    bmap[root] = 1;\n", "\n"),
-    "root_parent_unset": ("    pred[root] = root;\n", "\n"),
+    "distance_not_incremented": ("level[y] = dx + 1;", "level[y] = dx;"),
+    "distance_fixed_at_one": ("level[y] = dx + 1;", "level[y] = 1;"),
+    "drops_last_edge": ("for (int64_t e = a; e < b; ++e) {", "for (int64_t e = a; e < b - 1; ++e) {"),
+    "wrong_neighbour_index": ("const int32_t y = col[e];", "const int32_t y = col[e > a ? e - 1 : e];"),
+    "no_visited_test": ("if (level[y] < 0) {", "if (level[y] <= 0) {"),
+    "parent_is_self": ("parent[y] = x;", "parent[y] = y;"),
+    "root_not_marked": ("    level[root] = 0;\n", "\n"),
+    "root_parent_unset": ("    parent[root] = root;\n", "\n"),
+    "lifo_not_fifo": ("const int32_t x = fifo[head++];", "const int32_t x = fifo[--tail];"),
+    "wrong_level_count": ("frontier_sizes[level[fifo[i]]]++;", "frontier_sizes[level[fifo[i]] / 2]++;"),
 }
 
 VALIDATOR_MUTANTS = {
@@ -179,7 +180,7 @@ def _in_child(fn, so_path):
 
 def test_unmutated_passes(tmp_path):
     shutil.copy(SRC, tmp_path / "orig.c")
-    build_mutant(tmp_path, "orig", "int32_t lvl = 1;", "int32_t lvl = 1;")
+    build_mutant(tmp_path, "orig", "level[y] = dx + 1;", "level[y] = dx + 1;")
     so = str(tmp_path / "orig.so")
     assert _in_child(pins_pass, so) is True
     assert _in_child(validator_negatives_all_fail, so) is True

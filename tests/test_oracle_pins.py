@@ -349,16 +349,33 @@ def test_validator_reach_outside_component(g12):
     assert _val(g, r, lv, pa) == 2
 
 
-def test_validator_component_check_alone():
-    # a 2-vertex graph where both vertices are isolated; mark vertex 1 as the
-    # root and vertex 0 as reached with parent 1 and no edge: V2; with the
-    # edge present but the root's component check broken: V4 / V5.
-    g = graphgen.from_edges(4, [0, 2], [1, 3])
-    res = oracle.bfs(g.off, g.col, 0)
-    lv, pa = res.level.copy(), res.parent.copy()
-    lv[2], lv[3], pa[2], pa[3] = 3, 4, 2, 2
-    # 2 is reached with parent itself (a self-edge does not exist) -> V2
-    assert _val(g, 0, lv, pa) == 2
+def test_validator_component_cross_check():
+    # V2 + V3 tie every reached vertex to the root and V4 closes the reached
+    # set under adjacency, so on a consistent result the reached set already
+    # is the root's component and V5 cannot be the first check to fail.  V5
+    # is a cross-check against labels from an independent algorithm: it
+    # accepts union-find labels of the same graph and rejects labels that
+    # disagree with the reached set.
+    g = graphgen.from_edges(6, [0, 1, 3], [1, 2, 4])  # {0,1,2} {3,4} {5}
+    comp = oracle.components(g.off, g.col)
+    assert comp.tolist() == [0, 0, 0, 3, 3, 5]
+    res = oracle.bfs(g.off, g.col, 1)
+    assert oracle.validate(g.off, g.col, 1, res.level, res.parent, comp=comp)[0] == 0
+    wrong = comp.copy()
+    wrong[3] = 0  # labels claiming 3 shares the root's component
+    assert oracle.validate(g.off, g.col, 1, res.level, res.parent, comp=wrong) == (5, 3)
+    wrong = comp.copy()
+    wrong[2] = 5  # labels claiming 2 is elsewhere
+    assert oracle.validate(g.off, g.col, 1, res.level, res.parent, comp=wrong) == (5, 2)
+
+
+def test_reached_set_is_the_component_rmat():
+    g = graphgen.rmat(12, edgefactor=4)
+    comp = oracle.components(g.off, g.col)
+    for r in graphgen.pick_roots(g, 6, 17):
+        res = oracle.bfs(g.off, g.col, int(r))
+        assert np.array_equal(res.level >= 0, comp == comp[int(r)])
+        assert oracle.validate(g.off, g.col, int(r), res.level, res.parent, comp=comp)[0] == 0
 
 
 def test_validator_unreached_with_parent(g12):
