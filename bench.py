@@ -8,18 +8,33 @@ counts the undirected edges of the traversed component (half the directed
 CSR entries scanned) over the search time; the value is the harmonic mean
 over the timed steps, as the paper reports TEPS (Section 4).
 
-The JSON line also carries:
-  roofline     -- the expansion kernel's algorithmic bytes / its summed
-                  duration (HIP events around each launch, same stream),
-                  against the MI355X HBM peak of 8 TB/s;
-  cpu_baseline -- the serial CPU oracle on one root of the same graph, on
-                  this host's cores (one thread), in GTEPS;
-  grid         -- single-root searches on the 4096 x 4096 grid (GTEPS);
-  batch        -- 64 roots in one multi-source batch on R-MAT scale 22:
-                  roots/s, and the speedup over 64 one-at-a-time searches;
-  serve        -- open-loop Poisson queries (2000/s) over 32 resident graphs
-                  (24 R-MAT scales 14-22, 8 grids 256k x 256k): p50/p99
-                  latency (completion - scheduled arrival) and completed QPS.
+The headline pass runs with no per-kernel events.  The JSON line also
+carries:
+  roofline      -- the expansion kernel k_expand from a second, profiled pass
+                   over the same roots: the method's algorithmic bytes for its
+                   launches (4 per frontier edge of those levels, row-skipped
+                   ones included, + level and parent of each discovered
+                   vertex) over their summed duration (HIP events around each
+                   launch, on its stream), against the MI355X HBM peak of
+                   8 TB/s; the bytes it actually streams are reported beside;
+  plain_topdown -- the same searches without the row prefix skip (the plain
+                   top-down expansion of Algorithm 3), GTEPS and roofline;
+  cpu_baseline  -- the serial CPU oracle on every bench root of the same graph,
+                   one search per host thread: all-cores GTEPS and roots/s,
+                   the serial time per root, the CPU model and core count;
+  parity        -- every bench root's levels against the oracle (exact) and
+                   its parents through the oracle's validator;
+  configs       -- plain single-root searches on R-MAT scales 16 (16 roots)
+                   and 22 (64 roots), GTEPS and parity of every root;
+  grid          -- single-root searches on the 4096 x 4096 grid (GTEPS),
+                   every root's levels against the Manhattan distance;
+  batch         -- 64 roots in one multi-source batch on R-MAT scale 22:
+                   roots/s, the speedup over 64 one-at-a-time searches, every
+                   row against the oracle;
+  serve         -- open-loop Poisson queries (2000/s) over 32 resident graphs
+                   (24 R-MAT scales 14-22, 8 grids 256k x 256k): p50/p99
+                   latency (completion - scheduled arrival), completed QPS,
+                   and sampled results against the oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--scale S]
 """
@@ -93,6 +108,82 @@ def recorded_traffic(kernel_hash):
         return None
 
 
+def timed_pass(bfsmi, G, roots, levels, parents, steps, log_steps=False):
+    """steps searches over the roots in turn (host wall time of each
+    synchronous bfs_run).  Returns (per-step seconds, stats, total seconds)."""
+    stats, times = [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        r = int(roots[i % len(roots)])
+        ts = time.perf_counter()
+        st = bfsmi.bfs_run(G.handle, r, levels, parents)
+        times.append(time.perf_counter() - ts)
+        stats.append(st)
+        if log_steps:
+            log("step %d root %d: %.3f ms, levels %d (bitmap %d), reached %d, E_r %d, %.1f GTEPS"
+                % (i, r, times[-1] * 1e3, st.levels, st.bitmap_levels, st.reached,
+                   st.edges_scanned, st.edges_scanned / 2 / times[-1] / 1e9))
+    return times, stats, time.perf_counter() - t0
+
+
+def roofline_of(bfsmi, G, stats, V, kernel_hash):
+    """Roofline of the expansion kernel from a profiled pass: the method's
+    algorithmic bytes for its launches (4 per frontier edge of those levels,
+    skipped ones included, + level and parent per discovered vertex) over
+    their summed duration (HIP events on the launch stream)."""
+    x_alg = sum(st.expand_alg_bytes for st in stats)
+    x_str = sum(st.expand_bytes for st in stats)
+    x_ms = sum(st.expand_ms for st in stats)
+    x_launch = sum(st.expand_launches for st in stats)
+    achieved = x_alg / (x_ms * 1e-3) / 1e9 if x_ms > 0 else 0.0
+    streamed = x_str / (x_ms * 1e-3) / 1e9 if x_ms > 0 else 0.0
+    ept = bfsmi.bfs_get_option(G.handle, bfsmi.BFS_OPT_EDGES_PER_THREAD)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(kernel_hash),
+            "source_hash": kernel_hash,
+            "kernel": "k_expand<%d>" % ept,
+            "launches": x_launch,
+            "avg_launch_ms": round(x_ms / max(x_launch, 1), 5),
+            "alg_bytes_per_launch": x_alg // max(x_launch, 1),
+            "streamed_bytes_per_launch": x_str // max(x_launch, 1),
+            "streamed_gbs": round(streamed, 1),
+            "streamed_frac": round(streamed / HBM_PEAK_GBS, 4)}
+
+
+def search_summary(times, stats, V):
+    teps = [st.edges_scanned / 2 / dt / 1e9 for st, dt in zip(stats, times)]
+    # whole-search algorithmic bytes: init 8.125 V, 32 per reached vertex,
+    # 4 per directed edge of the component
+    b_alg = [8.125 * V + 32 * st.reached + 4 * st.edges_scanned for st in stats]
+    gbs = sum(b_alg) / sum(times) / 1e9
+    return {"gteps": round(harmonic_mean(teps), 3),
+            "median_gteps": round(sorted(teps)[len(teps) // 2], 3),
+            "ms_per_root": round(1e3 * sum(times) / len(times), 4),
+            "bfs_alg_gbs": round(gbs, 1), "bfs_roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def check_against_oracle(bfsmi, torch, g, G, roots, digest, parents=True, label=""):
+    """Every root's GPU levels equal the oracle's and its parents pass the
+    validator; results are checked on host threads in groups of 16."""
+    from oracle import parallel
+    levels = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    par = torch.empty(g.V, dtype=torch.int32, device="cuda") if parents else None
+    ok, n = 0, 0
+    for i in range(0, len(roots), 16):
+        items = []
+        for r in roots[i:i + 16]:
+            bfsmi.bfs_run(G.handle, int(r), levels, par)
+            torch.cuda.synchronize()
+            items.append((int(r), levels.cpu().numpy(),
+                          par.cpu().numpy() if parents else None))
+        checks = parallel.check_roots(g.off, g.col, items, digest=digest)
+        ok += sum(c.ok for c in checks)
+        n += len(checks)
+    log("%s: %d of %d roots equal the oracle (levels exact, parents valid)" % (label, ok, n))
+    return {"roots_checked": n, "roots_ok": ok}
+
+
 def single_root(args, torch, np, graphgen, bfsmi):
     t = time.time()
     g = graphgen.rmat(args.scale)
@@ -118,79 +209,107 @@ def single_root(args, torch, np, graphgen, bfsmi):
         log("autotuned configuration: %s" % tuned)
     if args.ept:
         G.set_option(bfsmi.BFS_OPT_EDGES_PER_THREAD, args.ept)
-    G.set_option(bfsmi.BFS_OPT_PROFILE, 1)
+    G.set_option(bfsmi.BFS_OPT_PROFILE, 0)
     levels = torch.empty(g.V, dtype=torch.int32, device="cuda")
     parents = torch.empty(g.V, dtype=torch.int32, device="cuda")
     for i in range(args.warmup):
         bfsmi.bfs_run(G.handle, int(roots[i % len(roots)]), levels, parents)
     torch.cuda.synchronize()
 
-    stats, times = [], []
+    # headline: plain timing, no per-kernel events
+    times, stats, total = timed_pass(bfsmi, G, roots, levels, parents, args.steps, log_steps=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        r = int(roots[i % len(roots)])
-        ts = time.perf_counter()
-        st = bfsmi.bfs_run(G.handle, r, levels, parents)
-        times.append(time.perf_counter() - ts)
-        stats.append(st)
-        log("step %d root %d: %.3f ms, levels %d (bitmap %d), reached %d, E_r %d, %.1f GTEPS"
-            % (i, r, times[-1] * 1e3, st.levels, st.bitmap_levels, st.reached, st.edges_scanned,
-               st.edges_scanned / 2 / times[-1] / 1e9))
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    res = search_summary(times, stats, g.V)
+    res["ms_per_step"] = total * 1e3 / args.steps
+    res["levels"] = stats[0].levels
+    res["reached"] = stats[0].reached
+    res["edges_scanned"] = stats[0].edges_scanned
+    khash = kernel_source_hash()
 
-    teps = [st.edges_scanned / 2 / dt / 1e9 for st, dt in zip(stats, times)]
-    gteps = harmonic_mean(teps)
-    x_bytes = sum(st.expand_bytes for st in stats)
-    x_ms = sum(st.expand_ms for st in stats)
-    x_launch = sum(st.expand_launches for st in stats)
-    achieved = x_bytes / (x_ms * 1e-3) / 1e9 if x_ms > 0 else 0.0
-    # whole-search algorithmic bytes: init 8.125 V, 32 per reached vertex,
-    # 4 per scanned directed edge
-    b_alg = [8.125 * g.V + 32 * st.reached + 4 * st.edges_scanned for st in stats]
-    bfs_gbs = sum(b_alg) / sum(times) / 1e9
-    breakdown = {k: round(sum(getattr(st, k) for st in stats) / len(stats), 4)
-                 for k in ("init_ms", "scan_ms", "expand_ms", "compact_ms", "device_ms")}
-    res = {
-        "gteps": gteps,
-        "ms_per_step": total * 1e3 / args.steps,
-        "median_gteps": sorted(teps)[len(teps) // 2],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(kernel_source_hash()),
-                     "source_hash": kernel_source_hash(),
-                     "kernel": "k_expand<%d>" % bfsmi.bfs_get_option(G.handle, bfsmi.BFS_OPT_EDGES_PER_THREAD),
-                     "launches": x_launch,
-                     "avg_launch_ms": round(x_ms / max(x_launch, 1), 5),
-                     "alg_bytes_per_launch": x_bytes // max(x_launch, 1)},
-        "bfs_alg_gbs": round(bfs_gbs, 1),
-        "bfs_roofline_frac": round(bfs_gbs / HBM_PEAK_GBS, 4),
-        "breakdown_ms_per_root": breakdown,
-        "levels": stats[0].levels if stats else 0,
-        "reached": stats[0].reached if stats else 0,
-        "edges_scanned": stats[0].edges_scanned if stats else 0,
-    }
+    # roofline and breakdown: the same roots again with per-kernel HIP events
+    G.set_option(bfsmi.BFS_OPT_PROFILE, 1)
+    ptimes, pstats, _ = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
+    G.set_option(bfsmi.BFS_OPT_PROFILE, 0)
+    res["roofline"] = roofline_of(bfsmi, G, pstats, g.V, khash)
+    res["roofline"]["pass"] = ("profiled pass over the %d roots, %.3f ms per search "
+                               "(headline pass %.3f ms)"
+                               % (len(roots), 1e3 * sum(ptimes) / len(ptimes),
+                                  res["ms_per_root"]))
+    res["breakdown_ms_per_root"] = {
+        k: round(sum(getattr(st, k) for st in pstats) / len(pstats), 4)
+        for k in ("init_ms", "scan_ms", "expand_ms", "compact_ms", "device_ms")}
+
+    # the plain top-down expansion of Algorithm 3 (no row prefix skip)
+    plain = None
+    if not args.no_degree_order:
+        G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 0)
+        bfsmi.bfs_run(G.handle, int(roots[0]), levels, parents)
+        t2, s2, tot2 = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
+        plain = search_summary(t2, s2, g.V)
+        G.set_option(bfsmi.BFS_OPT_PROFILE, 1)
+        _, ps2, _ = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
+        G.set_option(bfsmi.BFS_OPT_PROFILE, 0)
+        plain["roofline"] = roofline_of(bfsmi, G, ps2, g.V, khash)
+        plain["config"] = {"row_skip": False, "degree_order": True}
+        G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 1)
+        log("plain top-down (row skip off): %s" % plain)
+    res["plain_topdown"] = plain
 
     if not args.no_cpu_baseline:
-        import oracle
-        r0 = int(roots[0])
-        log("cpu baseline: serial oracle from root %d ..." % r0)
-        ts = time.perf_counter()
-        ref = oracle.bfs(g.off, g.col, r0)
-        dt = time.perf_counter() - ts
-        res["cpu_baseline"] = {"value": round(ref.edges_scanned / 2 / dt / 1e9, 5), "unit": "GTEPS",
-                               "cores": 1, "kind": "oracle",
-                               "sample": "1 root (%d) of the same R-MAT scale %d graph, serial C "
-                                         "oracle, %.1f s" % (r0, args.scale, dt),
-                               "cpu": cpu_model(), "host_cores": os.cpu_count()}
-        bfsmi.bfs_run(G.handle, r0, levels, parents)
-        torch.cuda.synchronize()
-        lv = levels.cpu().numpy()
-        res["parity_root0"] = bool(np.array_equal(lv, ref.level))
-        log("parity of root %d vs oracle: %s" % (r0, res["parity_root0"]))
+        from oracle import parallel
+        nthreads = parallel.default_workers(len(roots))
+        digest = parallel.csr_digest(g.off, g.col, nthreads)
+        log("cpu baseline: serial oracle, %d roots on %d host threads ..." % (len(roots), nthreads))
+        ref, wall, used = parallel.bfs_roots(g.off, g.col, [int(r) for r in roots],
+                                             workers=nthreads, fresh=True, digest=digest)
+        serial = [x.seconds for x in ref]
+        edges = sum(x.edges_scanned for x in ref)
+        res["cpu_baseline"] = {
+            "value": round(edges / 2 / wall / 1e9, 5), "unit": "GTEPS", "cores": used,
+            "kind": "oracle",
+            "sample": "the %d bench roots of the same R-MAT scale %d graph, one serial oracle "
+                      "search per host thread, %.1f s wall" % (len(roots), args.scale, wall),
+            "roots_per_s_all_cores": round(len(roots) / wall, 4),
+            "serial_s_per_root": round(sum(serial) / len(serial), 3),
+            "serial_gteps": round(harmonic_mean([x.edges_scanned / 2 / x.seconds / 1e9
+                                                 for x in ref]), 5),
+            "cpu": cpu_model(), "nproc": os.cpu_count()}
+        del ref
+        res["parity"] = check_against_oracle(bfsmi, torch, g, G, [int(r) for r in roots],
+                                             digest, label="rmat%d default" % args.scale)
+        if plain is not None:
+            G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 0)
+            res["parity_plain_topdown"] = check_against_oracle(
+                bfsmi, torch, g, G, [int(r) for r in roots], digest,
+                label="rmat%d row skip off" % args.scale)
+            G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 1)
     G.close()
     return res, g
+
+
+def small_config(scale, nroots, args, torch, np, graphgen, bfsmi):
+    """Plain single-root searches (levels and parents) on a smaller R-MAT
+    graph, every root timed and checked against the oracle."""
+    from oracle import parallel
+    g = graphgen.rmat(scale)
+    roots = [int(r) for r in graphgen.pick_roots(g, nroots, graphgen.root_seed(scale))]
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    levels = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    parents = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    for r in roots[:2]:
+        bfsmi.bfs_run(G.handle, r, levels, parents)
+    torch.cuda.synchronize()
+    times, stats, _ = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
+    res = {"graph": "rmat%d" % scale, "V": g.V, "nnz": g.nnz, "roots": len(roots),
+           "parents": True}
+    res.update(search_summary(times, stats, g.V))
+    res["levels_max"] = max(st.levels for st in stats)
+    digest = parallel.csr_digest(g.off, g.col)
+    res["parity"] = check_against_oracle(bfsmi, torch, g, G, roots, digest,
+                                         label="rmat%d" % scale)
+    G.close()
+    log("rmat%d single roots: %s" % (scale, res))
+    return res
 
 
 def grid_section(args, torch, np, graphgen, bfsmi):
@@ -205,9 +324,6 @@ def grid_section(args, torch, np, graphgen, bfsmi):
     pa = torch.empty(g.V, dtype=torch.int32, device="cuda")
     bfsmi.bfs_run(G.handle, roots[0], lv, pa)
     torch.cuda.synchronize()
-    r0, c0 = divmod(roots[0], w)
-    rr, cc = np.divmod(np.arange(g.V, dtype=np.int64), w)
-    ok = bool(np.array_equal(lv.cpu().numpy(), np.abs(rr - r0) + np.abs(cc - c0)))
     teps, levels, times = [], [], []
     for r in roots:
         t0 = time.perf_counter()
@@ -216,11 +332,24 @@ def grid_section(args, torch, np, graphgen, bfsmi):
         times.append(dt)
         teps.append(st.edges_scanned / 2 / dt / 1e9)
         levels.append(st.levels)
+    # every root: levels equal the Manhattan distance (closed form), parents
+    # pass the oracle's validator
+    from oracle import validate
+    rr, cc = np.divmod(np.arange(g.V, dtype=np.int64), w)
+    ok = 0
+    for r in roots:
+        bfsmi.bfs_run(G.handle, r, lv, pa)
+        torch.cuda.synchronize()
+        r0, c0 = divmod(r, w)
+        a = lv.cpu().numpy()
+        ok += bool(np.array_equal(a, np.abs(rr - r0) + np.abs(cc - c0))) and \
+            validate(g.off, g.col, r, a, pa.cpu().numpy())[0] == 0
     G.close()
     res = {"graph": "grid%dx%d" % (w, w), "roots": len(roots), "gteps": round(harmonic_mean(teps), 4),
            "ms_per_root": round(1e3 * sum(times) / len(times), 2),
            "levels_min": int(min(levels)), "levels_max": int(max(levels)),
-           "root0_matches_manhattan": ok}
+           "parity": {"roots_checked": len(roots), "roots_ok": int(ok),
+                      "check": "levels = Manhattan distance, parents validated"}}
     log("grid: %s" % res)
     return res
 
@@ -250,19 +379,18 @@ def batch_section(args, torch, np, graphgen, bfsmi):
         bfsmi.bfs_run(G.handle, r, lv, None)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    # rows vs the single-root path for a few roots (GPU against GPU; the
-    # oracle comparisons live in the tests)
-    ok = True
+    # every row against the oracle (the scale-22 single-root section has
+    # usually cached these roots already)
+    from oracle import parallel
     rows = out.cpu().numpy()
-    for i in (0, 31, 63):
-        bfsmi.bfs_run(G.handle, roots[i], lv, None)
-        torch.cuda.synchronize()
-        ok &= bool(np.array_equal(rows[i].astype(np.int32), lv.cpu().numpy()))
+    ref, _, _ = parallel.bfs_roots(g.off, g.col, roots)
+    ok = sum(bool(np.array_equal(rows[i].astype(np.int32), x.level)) for i, x in enumerate(ref))
     G.close()
     res = {"graph": "rmat%d" % scale, "n_roots": 64, "batch_ms": round(t_batch * 1e3, 3),
            "roots_per_s": round(64 / t_batch, 1), "sequential_roots_per_s": round(64 / t_seq, 1),
            "speedup_vs_sequential": round(t_seq / t_batch, 2), "union_levels": st.levels,
-           "union_edges_scanned": st.edges_scanned, "rows_match_single_root": ok}
+           "union_edges_scanned": st.edges_scanned,
+           "parity": {"rows_checked": len(roots), "rows_ok": int(ok)}}
     log("batch: %s" % res)
     return res
 
@@ -292,6 +420,7 @@ def serve_section(args, torch, np, graphgen, bfsmi):
     gsel = arr.integers(0, len(graphs), size=n)
     rsel = arr.random(size=n)
     pending = {}
+    samples = []
     rec = []  # (kind, arrive->done ms, arrive->admit ms, admit->done ms, lanes, levels)
     done_in_window = 0
     t_start = time.monotonic_ns()
@@ -309,12 +438,16 @@ def serve_section(args, torch, np, graphgen, bfsmi):
             cand = nonzero[gi]
             root = int(cand[int(rsel[i] * len(cand))])
             t = bfsmi.bfs_submit(s, ids[gi], root)
-            pending[t] = (sched, gi)
+            pending[t] = (sched, gi, root)
             sched += int(gaps[i] * 1e9)
             i += 1
         for t in bfsmi.bfs_server_completed(s):
-            arrive, gi = pending.pop(t)
+            arrive, gi, root = pending.pop(t)
             code, tm = bfsmi.bfs_poll(s, t, dst[gi])
+            if arrive >= warm_ns and len(rec) % 97 == 0 and len(samples) < 64:
+                # kept for the check against the oracle after the window (a
+                # device-side copy on the stream the delivery was ordered on)
+                samples.append((gi, root, dst[gi].clone()))
             if arrive >= warm_ns:
                 rec.append((kinds[gi], (tm.done_ns - arrive) / 1e6, (tm.admit_ns - arrive) / 1e6,
                             (tm.done_ns - tm.admit_ns) / 1e6, tm.lanes_in_batch, tm.levels))
@@ -329,6 +462,18 @@ def serve_section(args, torch, np, graphgen, bfsmi):
     bfsmi.bfs_server_destroy(s)
     for h in handles:
         h.close()
+    # sampled results against the oracle (levels, tolerance 0)
+    from oracle import parallel
+    torch.cuda.synchronize()
+    by_graph = {}
+    for gi, root, buf in samples:
+        by_graph.setdefault(gi, []).append((root, buf.cpu().numpy(), None))
+    s_ok, s_n = 0, 0
+    for gi, items in by_graph.items():
+        checks = parallel.check_roots(graphs[gi].off, graphs[gi].col, items, cache=False)
+        s_ok += sum(c.levels_equal for c in checks)
+        s_n += len(checks)
+    del samples
 
     def pct(xs, q):
         return round(float(np.percentile(xs, q)), 3) if len(xs) else None
@@ -338,7 +483,9 @@ def serve_section(args, torch, np, graphgen, bfsmi):
            "completed": len(rec), "qps": round(done_in_window / dur, 1),
            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
            "max_ms": round(max(lat), 3) if lat else None, "unfinished": len(pending),
-           "delivery": "int32 levels into a client device buffer"}
+           "delivery": "int32 levels into a client device buffer",
+           "parity": {"sampled_tickets": s_n, "tickets_ok": int(s_ok),
+                      "kinds": sorted({kinds[gi] for gi in by_graph})}}
     for kind in ("rmat", "grid"):
         sub = [r for r in rec if r[0] == kind]
         res[kind] = {"n": len(sub), "p50_ms": pct([r[1] for r in sub], 50),
@@ -375,6 +522,8 @@ def main():
     ap.add_argument("--summary", type=int, default=-1)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the scale-16 and scale-22 single-root configurations")
     ap.add_argument("--grid-side", type=int, default=4096)
     ap.add_argument("--grid-roots", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true")
@@ -426,6 +575,12 @@ def main():
     g_V, g_nnz = g.V, g.nnz
     del g
     release()
+    small = {}
+    if not args.no_small:
+        small["rmat16"] = small_config(16, 16, args, torch, np, graphgen, bfsmi)
+        release()
+        small["rmat22"] = small_config(22, 64, args, torch, np, graphgen, bfsmi)
+        release()
     grid = None if args.no_grid else grid_section(args, torch, np, graphgen, bfsmi)
     release()
     batch = None if args.no_batch else batch_section(args, torch, np, graphgen, bfsmi)
@@ -447,19 +602,26 @@ def main():
         "data": "synthetic R-MAT (seeded generator, Graph500 parameters), seeded roots",
         "config": {"workload": "rmat%d_single_root" % args.scale, "scale": args.scale,
                    "degree_order": not args.no_degree_order,
+                   "row_skip": not args.no_degree_order, "parents": True,
                    "edgefactor": 16, "A": 0.57, "B": 0.19, "C": 0.19, "V": g_V, "nnz": g_nnz,
                    "roots": args.roots, "levels_root0": res["levels"],
                    "reached_root0": res["reached"], "edges_scanned_root0": res["edges_scanned"]},
         "roofline": res["roofline"],
-        "median_gteps": round(res["median_gteps"], 3),
+        "median_gteps": res["median_gteps"],
         "bfs_alg_gbs": res["bfs_alg_gbs"],
         "bfs_roofline_frac": res["bfs_roofline_frac"],
         "breakdown_ms_per_root": res["breakdown_ms_per_root"],
         "context": {"paper_1xK20X_scale21_gteps": 1.13, "paper_4096xK20X_gteps": 830},
     }
+    if res.get("plain_topdown"):
+        out["plain_topdown"] = res["plain_topdown"]
     if "cpu_baseline" in res:
         out["cpu_baseline"] = res["cpu_baseline"]
-        out["parity_root0"] = res["parity_root0"]
+        out["parity"] = res["parity"]
+        if "parity_plain_topdown" in res:
+            out["parity_plain_topdown"] = res["parity_plain_topdown"]
+    if small:
+        out["configs"] = small
     if grid is not None:
         out["grid"] = grid
     if batch is not None:

@@ -119,6 +119,12 @@ typedef struct bfs_stats {
      * cumulative degree, its row offset) + 4 per discovered vertex for its
      * parent + 8 per discovered vertex in list mode (queue slot, level).  */
     int64_t expand_bytes;
+    /* The same launches' share of the search's algorithmic bytes (the
+     * roofline numerator): 4 * every frontier edge of those levels, the
+     * ones the row prefix skip drops included (their column ids are what
+     * the method reads), + 4 per discovered vertex for its level + 4 more
+     * for its parent when parents are requested.                         */
+    int64_t expand_alg_bytes;
 } bfs_stats;
 
 /* Thread-local message of the last failing call ("" if none). */
@@ -267,7 +273,11 @@ typedef struct bfs_server_stats {
 /* Counters since bfs_server_create (a consistent snapshot). */
 int bfs_server_get_stats(bfs_server *s, bfs_server_stats *out);
 
-/* Block until every submitted query has finished. */
+/* Block until every submitted query has finished.  Finished results hold
+ * arena memory until bfs_poll collects them, so queries can be left that no
+ * memory will ever admit; when no batch is running and the next query's
+ * batch state plus its result does not fit, drain returns BFS_ERR_BUDGET
+ * (poll the finished tickets, then drain again) instead of blocking. */
 int bfs_server_drain(bfs_server *s);
 
 /* Stop the worker thread and release the server (graphs stay valid). */

@@ -129,8 +129,8 @@ def _store(digest: str, res: RootResult) -> None:
         pass  # a cache that cannot be written only costs time
 
 
-def _one(off, col, root: int, digest: str | None) -> RootResult:
-    if digest is not None:
+def _one(off, col, root: int, digest: str | None, read: bool = True) -> RootResult:
+    if digest is not None and read:
         hit = _load_cached(digest, root)
         if hit is not None:
             return hit
@@ -143,16 +143,21 @@ def _one(off, col, root: int, digest: str | None) -> RootResult:
     return res
 
 
-def bfs_roots(off, col, roots, workers: int | None = None, cache: bool = True):
-    """Oracle levels for every root, one serial search per thread.
-    Returns (results in root order, wall seconds, threads used)."""
+def bfs_roots(off, col, roots, workers: int | None = None, cache: bool = True,
+              fresh: bool = False, digest: str | None = None):
+    """Oracle levels for every root, one serial search per thread.  With
+    fresh, every search runs (for timing) and its result is still stored
+    when cache is on.  Returns (results in root order, wall seconds,
+    threads used)."""
     off, col = _csr(off, col)
     roots = [int(r) for r in roots]
     n = default_workers(len(roots)) if workers is None else max(1, min(workers, len(roots) or 1))
-    digest = csr_digest(off, col, n) if cache else None
+    if cache and digest is None:
+        digest = csr_digest(off, col, n)
+    dig = digest if cache else None
     t = time.perf_counter()
     with ThreadPoolExecutor(max_workers=n) as ex:
-        out = list(ex.map(lambda r: _one(off, col, r, digest), roots))
+        out = list(ex.map(lambda r: _one(off, col, r, dig, not fresh), roots))
     return out, time.perf_counter() - t, n
 
 
@@ -175,7 +180,7 @@ class Check:
 
 
 def check_roots(off, col, items, workers: int | None = None, directed: bool = False,
-                comp=None, cache: bool = True):
+                comp=None, cache: bool = True, digest: str | None = None):
     """items: (root, levels, parents or None) triples from the path under
     test.  For each, the oracle's levels must equal `levels` element by
     element, and (levels, parents) must pass the tree validator.  Runs on a
@@ -183,7 +188,10 @@ def check_roots(off, col, items, workers: int | None = None, directed: bool = Fa
     off, col = _csr(off, col)
     items = list(items)
     n = default_workers(len(items)) if workers is None else max(1, min(workers, len(items) or 1))
-    digest = csr_digest(off, col, n) if cache else None
+    if cache and digest is None:
+        digest = csr_digest(off, col, n)
+    if not cache:
+        digest = None
 
     def run(it):
         root, lv, pa = it

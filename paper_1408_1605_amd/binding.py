@@ -62,7 +62,8 @@ class bfs_stats(ctypes.Structure):
                 ("device_ms", ctypes.c_double), ("init_ms", ctypes.c_double),
                 ("scan_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
                 ("compact_ms", ctypes.c_double), ("expand_launches", ctypes.c_int32),
-                ("device_loop_levels", ctypes.c_int32), ("expand_bytes", ctypes.c_int64)]
+                ("device_loop_levels", ctypes.c_int32), ("expand_bytes", ctypes.c_int64),
+                ("expand_alg_bytes", ctypes.c_int64)]
 
 
 class bfs_server_config(ctypes.Structure):
@@ -245,15 +246,13 @@ def bfs_poll(s: int, ticket: int, dst_levels=None):
     return code, tm
 
 
-_done_buf = (ctypes.c_uint64 * 4096)()
-
-
 def bfs_server_completed(s: int, max_tickets: int = 4096) -> list:
     """Tickets finished since the last call (each reported once)."""
     n = ctypes.c_int32(0)
-    m = min(max_tickets, len(_done_buf))
-    _check(load().bfs_server_completed(s, _done_buf, m, ctypes.byref(n)))
-    return list(_done_buf[:n.value])
+    m = max(1, int(max_tickets))
+    buf = (ctypes.c_uint64 * m)()  # per call: client threads share nothing
+    _check(load().bfs_server_completed(s, buf, m, ctypes.byref(n)))
+    return list(buf[:n.value])
 
 
 def bfs_server_get_stats(s: int) -> bfs_server_stats:

@@ -85,7 +85,7 @@ struct bfs_graph {
     int small_grid = 0;                       // its workgroups (0: not available)
     int32_t* h_roots = nullptr;         // pinned staging for batch roots
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // per-kernel timing
+    hipEvent_t pev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per-kernel timing
 
     // options
     int ept = 4;

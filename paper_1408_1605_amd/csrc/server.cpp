@@ -231,6 +231,9 @@ struct bfs_server {
     int64_t outstanding = 0;
     std::atomic<bool> stop{false};
     int worker_err = 0;
+    // no batch exists and the next query's batch state plus its result does
+    // not fit: only bfs_poll (which frees finished results) can make room
+    bool stalled = false;
     int persist_inflight = 0;         // worker thread only
     int ms_grid = 0;                  // persistent round workgroups (0: not available)
     bfs_server_stats stats{};
@@ -341,12 +344,27 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
 {
     const bfs_graph* g = G.g;
     SrvBatch* B = G.batch;
+    char* first_res = nullptr;  // reserved with a fresh batch for its first query
     if (!B) {
         if (G.pending.empty()) return false;
         int running = 0;
         for (const auto& o : graphs) running += o.batch != nullptr && o.batch->idle_since == 0;
         if (running >= cfg.max_inflight) return false;
-        char* mem = arena.alloc(G.state_bytes);
+        // a batch starts only when its state and its first query's result
+        // both fit: a batch that could admit nobody is never created
+        const size_t res_bytes = (size_t)g->V * 2;
+        auto take_both = [&](char** mem_out) {
+            char* m = arena.alloc(G.state_bytes);
+            char* r = m ? arena.alloc(res_bytes) : nullptr;
+            if (m && !r) {
+                arena.release(m);
+                m = nullptr;
+            }
+            *mem_out = m;
+            return r;
+        };
+        char* mem = nullptr;
+        first_res = take_both(&mem);
         if (!mem) {
             // release idle batches of other graphs, then retry once
             for (auto& o : graphs)
@@ -356,9 +374,21 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
                     delete o.batch;
                     o.batch = nullptr;
                 }
-            mem = arena.alloc(G.state_bytes);
+            first_res = take_both(&mem);
         }
-        if (!mem) return false;  // over budget: wait for memory to free up
+        if (!mem) {
+            // over budget: wait for memory to free up.  Running batches free
+            // theirs when their lanes end; with none left, only results that
+            // bfs_poll collects can make room.
+            bool any = false;
+            for (const auto& o : graphs) any |= o.batch != nullptr;
+            if (!any && !stalled) {
+                stalled = true;
+                idle_cv.notify_all();
+            }
+            return false;
+        }
+        stalled = false;
         B = carve_batch(mem, g);
         G.batch = B;
         P.fresh = true;
@@ -420,7 +450,8 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
         while (!G.pending.empty() && (~B->active & lane_cap)) {
             const uint64_t ticket = G.pending.front();
             SrvQuery& q = queries[ticket];
-            char* res = arena.alloc((size_t)g->V * 2);
+            char* res = first_res ? first_res : arena.alloc((size_t)g->V * 2);
+            first_res = nullptr;
             if (!res) break;
             G.pending.pop_front();
             const int b = __builtin_ctzll(~B->active & lane_cap);
@@ -435,6 +466,10 @@ bool bfs_server::plan_step(SrvGraph& G, bool round_done, bool round_err, StepPla
             G.h_lane_out[b] = q.result;
             P.fill[P.n_join] = q.result;
             ++P.n_join;
+        }
+        if (first_res) {  // not expected: a fresh batch always admits its first query
+            arena.release(first_res);
+            first_res = nullptr;
         }
         if (P.n_join) {
             const int lanes = __builtin_popcountll(B->active);
@@ -572,7 +607,7 @@ void bfs_server::run()
         std::unique_lock<std::mutex> lk(mu);
         bool waiting = false;
         for (const auto& G : graphs) waiting |= G.batch != nullptr || !G.pending.empty();
-        if (waiting) {
+        if (waiting && !stalled) {
             // poll in-flight rounds at a fine grain
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -773,6 +808,7 @@ int bfs_poll(bfs_server* s, uint64_t ticket, int32_t* dst_levels, bfs_timing* tm
     if (it != s->queries.end()) {
         s->arena.release(reinterpret_cast<char*>(it->second.result));
         s->queries.erase(it);
+        s->stalled = false;  // the worker retries admission
     }
     s->cv.notify_one();
     return rc == BFS_OK ? ok() : rc;
@@ -806,8 +842,15 @@ int bfs_server_drain(bfs_server* s)
 {
     if (!s) return fail(BFS_ERR_INVALID, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    s->idle_cv.wait(lk, [s] { return s->outstanding <= 0 || s->worker_err != 0; });
+    s->idle_cv.wait(lk, [s] {
+        return s->outstanding <= 0 || s->worker_err != 0 || s->stalled;
+    });
     if (s->worker_err) return fail(s->worker_err, "server worker failed");
+    if (s->outstanding > 0)
+        return fail(BFS_ERR_BUDGET,
+                    "%lld queries cannot start: the arena is held by finished results that "
+                    "have not been collected with bfs_poll",
+                    (long long)s->outstanding);
     return ok();
 }
 

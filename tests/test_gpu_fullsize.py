@@ -1,14 +1,19 @@
-"""Parity at the workloads' full sizes, in the launch configuration that
-bench.py times (degree-ordered graph, default options).
+"""Parity at the workloads' full sizes, with the roots and the launch
+configuration that bench.py times (degree-ordered graphs, default options).
 
-R-MAT scale 26 (V = 2^26, ~2.1e9 directed entries): one root, levels
-compared with the serial oracle element by element, parents checked by the
-tree validator.  4096 x 4096 grid: levels equal the Manhattan distance for
-two roots.  R-MAT scale 22: four single roots and a 64-root batch against
-the oracle.
+  R-MAT scale 26 (V = 2^26, ~2.1e9 directed entries): all 16 bench roots,
+    with and without the row prefix skip;
+  4096 x 4096 grid: all 16 bench roots (levels = Manhattan distance, parents
+    validated);
+  R-MAT scale 22: all 64 bench roots as single-root searches, and the
+    64-root batch;
+  R-MAT scale 16: all 16 bench roots.
+Levels are compared with the serial oracle element by element, parents are
+checked by the tree validator, and each search's level / reached / edge
+counts must equal the oracle's.  The oracle runs on a pool of host threads
+(one serial search per thread) with its results cached by (graph, root).
 """
 import os
-import sys
 import time
 
 import numpy as np
@@ -16,16 +21,13 @@ import pytest
 
 import graphgen
 import oracle
+from oracle import parallel
+from parity_util import assert_parity, gpu_results, manhattan, say
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(os.environ.get("BFSMI_BIG", "1") == "0",
                                  reason="full-size graphs disabled (BFSMI_BIG=0)")]
 torch = pytest.importorskip("torch")
-
-
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
@@ -37,60 +39,68 @@ def bfsmi():
     return p
 
 
-def test_rmat26_root_matches_oracle(bfsmi):
+def test_rmat26_all_bench_roots(bfsmi):
     t = time.time()
     g = graphgen.rmat(26)
-    _say("rmat26 generated in %.1fs, nnz=%d" % (time.time() - t, g.nnz))
-    root = int(graphgen.pick_roots(g, 1, graphgen.root_seed(26))[0])
+    say("rmat26 generated in %.1fs, nnz=%d" % (time.time() - t, g.nnz))
+    roots = [int(r) for r in graphgen.pick_roots(g, 16, graphgen.root_seed(26))]
     G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
-    lv, pa, st = G.run(root)
-    torch.cuda.synchronize()
-    lv, pa = lv.cpu().numpy(), pa.cpu().numpy()
-    # the same search without the row prefix skip
+    digest = parallel.csr_digest(g.off, g.col)
+    items = gpu_results(torch, G, roots)
+    say("rmat26: 16 GPU searches done")
+    assert_parity(g, items, digest=digest, label="rmat26 default")
+    del items
+    # the plain top-down expansion (no row prefix skip), as the bench's
+    # second headline runs it
     G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 0)
-    lv2, _, st2 = G.run(root, want_parents=False)
-    torch.cuda.synchronize()
-    lv2 = lv2.cpu().numpy()
+    items = gpu_results(torch, G, roots)
+    assert_parity(g, items, digest=digest, label="rmat26 row skip off")
+    del items
     G.close()
-    _say("gpu done: levels %d reached %d" % (st.levels, st.reached))
-    ref = oracle.bfs(g.off, g.col, root)
-    assert np.array_equal(lv, ref.level)
-    assert st.reached == ref.reached and st.edges_scanned == ref.edges_scanned
-    assert np.array_equal(lv2, ref.level) and st2.edges_scanned == ref.edges_scanned
-    code, bad = oracle.validate(g.off, g.col, root, lv, pa)
-    assert code == 0, (oracle.INVARIANTS[code], bad)
 
 
-def test_grid4096_manhattan(bfsmi):
+def test_grid4096_all_bench_roots(bfsmi):
     w = 4096
     g = graphgen.grid(w)
+    rng = np.random.default_rng(2000 + w)
+    roots = [int(x) for x in rng.choice(g.V, size=16, replace=False)]
     G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
-    r_, c_ = np.divmod(np.arange(g.V, dtype=np.int64), w)
-    for root in (0, (w // 2) * w + 123):
+    items = []
+    for r in roots:
         t = time.time()
-        lv, pa, st = G.run(root)
+        lv, pa, st = G.run(r)
         torch.cuda.synchronize()
-        _say("grid4096 root %d: %d levels in %.2fs" % (root, st.levels, time.time() - t))
-        r0, c0 = divmod(root, w)
-        assert np.array_equal(lv.cpu().numpy(), np.abs(r_ - r0) + np.abs(c_ - c0))
-        code, bad = oracle.validate(g.off, g.col, root, lv.cpu().numpy(), pa.cpu().numpy())
-        assert code == 0, (oracle.INVARIANTS[code], bad)
+        lv = lv.cpu().numpy()
+        # the closed form pins the levels independently of the oracle
+        assert np.array_equal(lv, manhattan(w, w, r)), r
+        items.append((r, lv, pa.cpu().numpy(), st))
+        say("grid4096 root %d: %d levels in %.2fs" % (r, st.levels, time.time() - t))
+    assert_parity(g, items, label="grid4096")
     G.close()
 
 
-def test_rmat22_roots_and_batch(bfsmi):
+def test_rmat22_all_single_roots_and_batch(bfsmi):
     g = graphgen.rmat(22)
-    roots = graphgen.pick_roots(g, 64, graphgen.root_seed(22))
+    roots = [int(r) for r in graphgen.pick_roots(g, 64, graphgen.root_seed(22))]
     G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER | bfsmi.BFS_WS_BATCH)
-    for r in roots[:4]:
-        lv, pa, st = G.run(int(r))
-        torch.cuda.synchronize()
-        ref = oracle.bfs(g.off, g.col, int(r))
-        assert np.array_equal(lv.cpu().numpy(), ref.level)
-        code, bad = oracle.validate(g.off, g.col, int(r), lv.cpu().numpy(), pa.cpu().numpy())
-        assert code == 0, (oracle.INVARIANTS[code], bad)
-    out, st = G.run_batch([int(r) for r in roots])
+    digest = parallel.csr_digest(g.off, g.col)
+    comp = oracle.components(g.off, g.col)
+    items = gpu_results(torch, G, roots)
+    assert_parity(g, items, digest=digest, comp=comp, label="rmat22 single roots")
+    del items
+    out, st = G.run_batch(roots)
     torch.cuda.synchronize()
-    exp = oracle.batch_levels_int8(g.off, g.col, roots)
-    assert np.array_equal(out.cpu().numpy(), exp)
+    got = out.cpu().numpy()
+    res, _, _ = parallel.bfs_roots(g.off, g.col, roots, digest=digest)
+    for i, x in enumerate(res):
+        assert np.array_equal(got[i].astype(np.int32), x.level), (i, roots[i])
+    G.close()
+
+
+def test_rmat16_all_bench_roots(bfsmi):
+    g = graphgen.rmat(16)
+    roots = [int(r) for r in graphgen.pick_roots(g, 16, graphgen.root_seed(16))]
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    comp = oracle.components(g.off, g.col)
+    assert_parity(g, gpu_results(torch, G, roots), comp=comp, label="rmat16")
     G.close()

@@ -326,3 +326,41 @@ def test_serve_wide_deep_rounds(bfsmi):
     assert st.persistent_rounds > 0 and st.wide_rounds > 0
     bfsmi.bfs_server_destroy(s)
     h.close()
+
+
+def test_serve_drain_reports_uncollected_results(bfsmi, pool):
+    # room for one batch state and three results: after three queries finish
+    # without being polled, nothing else can be admitted, so drain must
+    # report BFS_ERR_BUDGET instead of blocking; polling frees the room and
+    # the rest then completes, every result equal to the oracle's
+    graphs, handles = pool
+    g, h = graphs[0], handles[0]
+
+    def al(x):
+        return (x + 255) // 256 * 256
+    V = g.V
+    state = (4 * al(8 * V) + al((V + 31) // 32 * 4) + 4 * al(4 * V) + al(8 * (V + 1)) + al(8 * ((V + 2047) // 2048 + 1))
+             + al(4 * ((g.nnz + 255) // 256 + 2)) + al(128) + al(512) + al(256) + al(512))
+    s, ids, arena = make_server(bfsmi, [h], arena_bytes=state + 3 * al(2 * V) + 256)
+    roots = [int(r) for r in graphgen.pick_roots(g, 40, 5)]
+    ts = [bfsmi.bfs_submit(s, ids[0], r) for r in roots]
+    t0 = time.time()
+    with pytest.raises(bfsmi.BFSError) as e:
+        bfsmi.bfs_server_drain(s)
+    assert e.value.code == bfsmi.BFS_ERR_BUDGET
+    _say("drain reported the stall after %.3f s" % (time.time() - t0))
+    assert time.time() - t0 < 30
+    done = {}
+    while len(done) < len(ts):
+        for t in bfsmi.bfs_server_completed(s):
+            buf = np.empty(V, dtype=np.int32)
+            code, _ = bfsmi.bfs_poll(s, t, buf)
+            assert code == bfsmi.BFS_OK
+            done[t] = buf
+        assert time.time() - t0 < 60, "queries did not finish"
+        time.sleep(0.001)
+    bfsmi.bfs_server_drain(s)  # nothing outstanding: returns at once
+    for t, r in zip(ts, roots):
+        assert np.array_equal(done[t], oracle.bfs(g.off, g.col, r).level), r
+    bfsmi.bfs_server_destroy(s)
+    del arena
