@@ -194,6 +194,31 @@ int bfs_run(bfs_graph *g, int32_t root, int32_t *d_levels, int32_t *d_parents,
 int bfs_run_batch(bfs_graph *g, const int32_t *h_roots, int32_t n_roots,
                   int8_t *d_levels, void *hip_stream, bfs_stats *st);
 
+/*
+ * Allocation-free single-root search, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same search as bfs_run on a plain
+ * (not degree-ordered) CSR, with no graph handle: every scratch array lives
+ * in one static device array of 32 MiB per device, held from the library's
+ * load until the process ends.  The call makes no device or pinned-host
+ * allocation and creates no events or streams.
+ *   d_row_offsets, d_col: the CSR as for bfs_graph_create (device, read
+ *                         only); offsets and column ids are checked on
+ *                         every call (BFS_ERR_INVALID)
+ *   root, d_levels, d_parents, st: as for bfs_run; st->device_ms is the
+ *                         host wall time of the call
+ * Size limit: the scratch needs about 32.25 * V + nnz / 64 + 2.2 MB bytes
+ * (V <= 524288 with nnz <= 2^28 always fits); larger inputs return
+ * BFS_ERR_WORKSPACE before any device work.
+ * Runs on the calling thread's current device; all pointers must be that
+ * device's.  Calls that overlap on one device share the array and race:
+ * serialise them.  Each call rewrites what it uses (the last call's
+ * contents are never read).
+ */
+int bfs_run_noalloc(int32_t V, int64_t nnz, const int64_t *d_row_offsets,
+                    const int32_t *d_col, int32_t root, int32_t *d_levels,
+                    int32_t *d_parents, void *hip_stream, bfs_stats *st);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: a resident pool of graphs, queries admitted by an HBM budget and
  * batched per graph into multi-source lanes at level boundaries.          */

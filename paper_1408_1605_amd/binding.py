@@ -47,6 +47,7 @@ EXPORTS = (
     "bfs_graph_destroy", "bfs_set_option", "bfs_get_option", "bfs_run", "bfs_run_batch",
     "bfs_server_create", "bfs_server_add_graph", "bfs_submit", "bfs_poll",
     "bfs_server_completed", "bfs_server_get_stats", "bfs_server_drain", "bfs_server_destroy",
+    "bfs_run_noalloc",
 )
 
 
@@ -121,6 +122,8 @@ def load(path: str = LIB_PATH):
         "bfs_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(bfs_server_stats)]),
         "bfs_server_drain": (ctypes.c_int, [vp]),
         "bfs_server_destroy": (ctypes.c_int, [vp]),
+        "bfs_run_noalloc": (ctypes.c_int, [i32, i64, vp, vp, i32, vp, vp, vp,
+                                           ctypes.POINTER(bfs_stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -196,6 +199,14 @@ def bfs_run(g: int, root: int, d_levels, d_parents=None, stream=None) -> bfs_sta
     st = bfs_stats()
     _check(load().bfs_run(g, root, _ptr(d_levels), _ptr(d_parents), _stream(stream),
                           ctypes.byref(st)))
+    return st
+
+
+def bfs_run_noalloc(V: int, nnz: int, d_row_offsets, d_col, root: int, d_levels,
+                    d_parents=None, stream=None) -> bfs_stats:
+    st = bfs_stats()
+    _check(load().bfs_run_noalloc(V, nnz, _ptr(d_row_offsets), _ptr(d_col), root, _ptr(d_levels),
+                                  _ptr(d_parents), _stream(stream), ctypes.byref(st)))
     return st
 
 

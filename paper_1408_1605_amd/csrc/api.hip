@@ -97,6 +97,71 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
     return L;
 }
 
+int small_loop_grid(int num_cus)
+{
+    // the persistent small-level loop needs all its workgroups resident: at
+    // most one per CU
+    return small_loop_blocks() > 0 ? std::min(kSmallWGs, num_cus) : 0;
+}
+
+// Points the handle's arrays into the workspace ws laid out as L.
+void bind_workspace(bfs_graph* g, char* ws, const WsLayout& L, uint32_t flags)
+{
+    g->L = L;
+    g->vis = reinterpret_cast<uint32_t*>(ws + L.vis);
+    g->vis_old = reinterpret_cast<uint32_t*>(ws + L.vis_old);
+    g->q[0] = reinterpret_cast<int32_t*>(ws + L.q0);
+    g->q[1] = reinterpret_cast<int32_t*>(ws + L.q1);
+    g->deg = reinterpret_cast<int32_t*>(ws + L.deg);
+    g->rowstart = reinterpret_cast<int64_t*>(ws + L.rowstart);
+    g->suid = reinterpret_cast<int32_t*>(ws + L.suid);
+    g->cumul = reinterpret_cast<int64_t*>(ws + L.cumul);
+    g->bsum = reinterpret_cast<int64_t*>(ws + L.bsum);
+    g->tile_k = reinterpret_cast<int32_t*>(ws + L.tile_k);
+    g->ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+    g->scratch = reinterpret_cast<int32_t*>(ws + L.scratch);
+    g->small_sync = reinterpret_cast<SmallSync*>(ws + L.sync);
+    {
+        const int32_t cap = small_side_cap(g->V);
+        char* b = ws + L.sside;
+        g->small_side.off[0] = reinterpret_cast<int64_t*>(b);
+        g->small_side.off[1] = reinterpret_cast<int64_t*>(b + (size_t)cap * 8);
+        g->small_side.deg[0] = reinterpret_cast<int32_t*>(b + (size_t)cap * 16);
+        g->small_side.deg[1] = reinterpret_cast<int32_t*>(b + (size_t)cap * 20);
+        g->small_side.id[0] = reinterpret_cast<int32_t*>(b + (size_t)cap * 24);
+        g->small_side.id[1] = reinterpret_cast<int32_t*>(b + (size_t)cap * 28);
+        g->small_side.cap = cap;
+    }
+    g->summary = reinterpret_cast<uint32_t*>(ws + L.summary);
+    {
+        // blocks of 2^shift ids, at most kSummaryMaxWords * 32 of them
+        int shift = 10;
+        while ((((int64_t)g->V + (1ll << shift) - 1) >> shift) > (int64_t)kSummaryMaxWords * 32) ++shift;
+        g->summary_shift = shift;
+        g->summary_blocks = (int32_t)(((int64_t)g->V + (1ll << shift) - 1) >> shift);
+        g->summary_words = (g->summary_blocks + 31) / 32;
+    }
+    g->s_off = g->off;
+    g->s_col = g->col;
+    if (flags & BFS_DEGREE_ORDER) {
+        g->rank = reinterpret_cast<int32_t*>(ws + L.rank);
+        g->orig = reinterpret_cast<int32_t*>(ws + L.orig);
+        g->s_off = reinterpret_cast<int64_t*>(ws + L.off_r);
+        g->s_col = reinterpret_cast<int32_t*>(ws + L.col_r);
+        g->skip = reinterpret_cast<int32_t*>(ws + L.skip);
+        g->lvl_int = reinterpret_cast<int32_t*>(ws + L.lvl_int);
+        g->par_int = reinterpret_cast<int32_t*>(ws + L.par_int);
+        if (flags & BFS_WS_BATCH) g->ms_out = reinterpret_cast<int8_t*>(ws + L.ms_out);
+    }
+    if (flags & BFS_WS_BATCH) {
+        g->ms_sn = reinterpret_cast<SeenNext*>(ws + L.ms_sn);
+        g->ms_front = reinterpret_cast<uint64_t*>(ws + L.ms_front);
+        g->ms_ctrl = reinterpret_cast<Ctrl*>(ws + L.ms_ctrl);
+        g->ms_roots = reinterpret_cast<int32_t*>(ws + L.ms_roots);
+        g->ms_touched = reinterpret_cast<uint32_t*>(ws + L.ms_touched);
+    }
+}
+
 }  // namespace bfsmi
 
 using namespace bfsmi;
@@ -157,59 +222,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
     g->ws_bytes = ws_bytes;
     g->flags = flags;
     g->device = dev;
-    g->L = L;
-    g->vis = reinterpret_cast<uint32_t*>(g->ws + L.vis);
-    g->vis_old = reinterpret_cast<uint32_t*>(g->ws + L.vis_old);
-    g->q[0] = reinterpret_cast<int32_t*>(g->ws + L.q0);
-    g->q[1] = reinterpret_cast<int32_t*>(g->ws + L.q1);
-    g->deg = reinterpret_cast<int32_t*>(g->ws + L.deg);
-    g->rowstart = reinterpret_cast<int64_t*>(g->ws + L.rowstart);
-    g->suid = reinterpret_cast<int32_t*>(g->ws + L.suid);
-    g->cumul = reinterpret_cast<int64_t*>(g->ws + L.cumul);
-    g->bsum = reinterpret_cast<int64_t*>(g->ws + L.bsum);
-    g->tile_k = reinterpret_cast<int32_t*>(g->ws + L.tile_k);
-    g->ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ctrl);
-    g->scratch = reinterpret_cast<int32_t*>(g->ws + L.scratch);
-    g->small_sync = reinterpret_cast<SmallSync*>(g->ws + L.sync);
-    {
-        const int32_t cap = small_side_cap(V);
-        char* b = g->ws + L.sside;
-        g->small_side.off[0] = reinterpret_cast<int64_t*>(b);
-        g->small_side.off[1] = reinterpret_cast<int64_t*>(b + (size_t)cap * 8);
-        g->small_side.deg[0] = reinterpret_cast<int32_t*>(b + (size_t)cap * 16);
-        g->small_side.deg[1] = reinterpret_cast<int32_t*>(b + (size_t)cap * 20);
-        g->small_side.id[0] = reinterpret_cast<int32_t*>(b + (size_t)cap * 24);
-        g->small_side.id[1] = reinterpret_cast<int32_t*>(b + (size_t)cap * 28);
-        g->small_side.cap = cap;
-    }
-    g->summary = reinterpret_cast<uint32_t*>(g->ws + L.summary);
-    {
-        // blocks of 2^shift ids, at most kSummaryMaxWords * 32 of them
-        int shift = 10;
-        while ((((int64_t)V + (1ll << shift) - 1) >> shift) > (int64_t)kSummaryMaxWords * 32) ++shift;
-        g->summary_shift = shift;
-        g->summary_blocks = (int32_t)(((int64_t)V + (1ll << shift) - 1) >> shift);
-        g->summary_words = (g->summary_blocks + 31) / 32;
-    }
-    g->s_off = d_row_offsets;
-    g->s_col = d_col;
-    if (flags & BFS_DEGREE_ORDER) {
-        g->rank = reinterpret_cast<int32_t*>(g->ws + L.rank);
-        g->orig = reinterpret_cast<int32_t*>(g->ws + L.orig);
-        g->s_off = reinterpret_cast<int64_t*>(g->ws + L.off_r);
-        g->s_col = reinterpret_cast<int32_t*>(g->ws + L.col_r);
-        g->skip = reinterpret_cast<int32_t*>(g->ws + L.skip);
-        g->lvl_int = reinterpret_cast<int32_t*>(g->ws + L.lvl_int);
-        g->par_int = reinterpret_cast<int32_t*>(g->ws + L.par_int);
-        if (flags & BFS_WS_BATCH) g->ms_out = reinterpret_cast<int8_t*>(g->ws + L.ms_out);
-    }
-    if (flags & BFS_WS_BATCH) {
-        g->ms_sn = reinterpret_cast<SeenNext*>(g->ws + L.ms_sn);
-        g->ms_front = reinterpret_cast<uint64_t*>(g->ws + L.ms_front);
-        g->ms_ctrl = reinterpret_cast<Ctrl*>(g->ws + L.ms_ctrl);
-        g->ms_roots = reinterpret_cast<int32_t*>(g->ws + L.ms_roots);
-        g->ms_touched = reinterpret_cast<uint32_t*>(g->ws + L.ms_touched);
-    }
+    bind_workspace(g, g->ws, L, flags);
 
     auto cleanup = [&](int code) {
         bfs_graph_destroy(g);
@@ -224,12 +237,7 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         return cleanup(fail(BFS_ERR_HIP, "hipGetDeviceProperties failed"));
     }
     g->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    {
-        // the persistent small-level loop needs all its workgroups resident:
-        // at most one per CU
-        const int per_cu = small_loop_blocks();
-        g->small_grid = per_cu > 0 ? std::min(kSmallWGs, g->num_cus) : 0;
-    }
+    g->small_grid = small_loop_grid(g->num_cus);
 
     // pinned host block: [Ctrl][Ctrl for the batch][64 batch roots]
     hipError_t e = hipHostMalloc((void**)&g->h_ctrl, 2 * sizeof(Ctrl) + 64 * sizeof(int32_t),
@@ -416,8 +424,10 @@ static float event_ms(hipEvent_t a, hipEvent_t b)
 
 // The level loop for one root: heavy levels are driven from the host (one
 // control-block read per level, per-level choices of summary and frontier
-// form); runs of small levels go to the device loop.
-static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
+// form); runs of small levels go to the device loop.  A handle without
+// events (the allocation-free entry point) skips the event timing and
+// profiling and ends with a stream synchronisation instead.
+int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
                          hipStream_t s, bfs_stats* st)
 {
     const int tile = kWG * g->ept;
@@ -426,14 +436,15 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
     const int grid_cap = g->num_cus * g->grid_wgs;
     // tile_k holds ceil(nnz / kMinTile) + 2 entries; ntiles + 1 must fit
     const int64_t tile_cap = (g->nnz + kMinTile - 1) / kMinTile + 1;
-    const bool prof = g->profile != 0;
+    const bool timed = g->ev0 != nullptr && g->ev1 != nullptr;
+    const bool prof = timed && g->profile != 0;
     bfs_stats acc{};
 
     // under degree order the search writes level / parent by internal id and
     // k_finish reorders them into the caller's arrays at the end
     int32_t* lv_s = g->rank ? g->lvl_int : levels;
     int32_t* pa_s = parents ? (g->rank ? g->par_int : parents) : nullptr;
-    BFS_HIP_TRY(hipEventRecord(g->ev0, s));
+    if (timed) BFS_HIP_TRY(hipEventRecord(g->ev0, s));
     BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, lv_s, pa_s, g->vis, g->vis_old,
                             g->q[0], g->ctrl, grid_cap, g->rank ? 0 : 1));
     const int32_t sum_words = g->summary_words;
@@ -543,8 +554,12 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
                                   parents));
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
     }
-    BFS_HIP_TRY(hipEventRecord(g->ev1, s));
-    BFS_HIP_TRY(hipEventSynchronize(g->ev1));
+    if (timed) {
+        BFS_HIP_TRY(hipEventRecord(g->ev1, s));
+        BFS_HIP_TRY(hipEventSynchronize(g->ev1));
+    } else {
+        BFS_HIP_TRY(hipStreamSynchronize(s));
+    }
     if (g->rank && prof) acc.compact_ms += event_ms(g->pev[0], g->pev[3]);
     if (prof) acc.init_ms = event_ms(g->ev0, g->pev[4]);
     if (st) {
@@ -553,7 +568,7 @@ static int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* p
         st->bitmap_levels = bitmap_levels;
         st->reached = reached;
         st->edges_scanned = edges;
-        st->device_ms = event_ms(g->ev0, g->ev1);
+        st->device_ms = timed ? event_ms(g->ev0, g->ev1) : 0.0;
         st->expand_launches = xlaunches;
         st->device_loop_levels = dev_levels;
         st->expand_bytes = xbytes;

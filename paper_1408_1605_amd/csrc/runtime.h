@@ -99,3 +99,20 @@ struct bfs_graph {
 
     std::atomic<int> busy{0};
 };
+
+namespace bfsmi {
+
+// Points the handle's arrays into the workspace ws laid out as L (and sets
+// the visited summary's block size from g->V).
+void bind_workspace(bfs_graph* g, char* ws, const WsLayout& L, uint32_t flags);
+
+// Single-root level loop on a bound handle; the caller holds the handle and
+// has made its device current.
+int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
+                  hipStream_t s, bfs_stats* st);
+
+// Workgroups of the persistent small-level loop on a device with num_cus
+// compute units (0: the loop is not available).
+int small_loop_grid(int num_cus);
+
+}  // namespace bfsmi

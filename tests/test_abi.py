@@ -171,3 +171,21 @@ def test_binding_structs_match_header(tmp_path):
             off, size = (int(x) for x in got["%s.%s" % (n, f)].split())
             desc = getattr(S, f)
             assert (off, size) == (desc.offset, desc.size), (n, f)
+
+
+def test_noalloc_size_limit(lib):
+    """bfs_run_noalloc's scratch is the plain workspace layout inside a
+    32 MiB static array: the sizes its declaration promises fit, and an
+    oversize input is refused before any device call."""
+    limit = 32 << 20
+    assert lib.bfs_workspace_bytes(524288, 1 << 28, 0) <= limit
+    for V, nnz in [(1, 0), (1000, 10**6), (1 << 19, 1 << 24)]:
+        assert lib.bfs_workspace_bytes(V, nnz, 0) <= 32.25 * V + nnz / 64 + 2.2e6
+    so = lib.load()
+    code = so.bfs_run_noalloc(1 << 22, 1 << 26, 256, 256, 0, 256, None, None, None)
+    assert code == lib.BFS_ERR_WORKSPACE
+    assert "static array" in lib.bfs_last_error()
+    # argument checks come first
+    assert so.bfs_run_noalloc(0, 0, 256, 256, 0, 256, None, None, None) == lib.BFS_ERR_INVALID
+    assert so.bfs_run_noalloc(10, 5, None, 256, 0, 256, None, None, None) == lib.BFS_ERR_INVALID
+    assert so.bfs_run_noalloc(10, 5, 256, 256, 10, 256, None, None, None) == lib.BFS_ERR_INVALID
