@@ -220,6 +220,80 @@ int bfs_run_noalloc(int32_t V, int64_t nnz, const int64_t *d_row_offsets,
                     int32_t *d_parents, void *hip_stream, bfs_stats *st);
 
 /* ---------------------------------------------------------------------- */
+/* In-GPU 2D blocking: the search of Algorithm 2 run by an R x C grid of
+ * virtual processors inside one GPU (Section 2.2 partitioning; local index
+ * maps LOCAL_ROW / LOCAL_COL / ROW2COL of Section 3.1; the expansion of
+ * Algorithm 3 with destinations grouped by owner column; the frontier
+ * update of Section 3.5; list or bitmap messages by the threshold of
+ * Section 5).  Vertex block p = j*R + i (B ids, B = ceil(V / RC) rounded up
+ * to a multiple of 32) is owned by processor (i, j); processor (i, j) holds
+ * the edges from column block j into row blocks m*R + i.  The column
+ * (expand) and row (fold) exchanges are device-local.  Processor p's kernels
+ * run on XCD p mod 8, so its bitmap of C*B local rows stays in one L2.   */
+
+typedef struct bfs_grid2d bfs_grid2d;
+
+/* bfs_grid2d_run msg_mode */
+#define BFS_2D_MSG_AUTO   0  /* per message, a list unless longer than the
+                                bitmap of the destination block (Section 5) */
+#define BFS_2D_MSG_LIST   1  /* lists only                                  */
+#define BFS_2D_MSG_BITMAP 2  /* bitmaps only (the bitmap-emitting expansion
+                                and update kernels every level)             */
+
+typedef struct bfs_grid2d_stats {
+    int32_t levels;        /* non-empty frontiers, the root's included        */
+    int32_t list_levels;   /* (processor, level) expansions that kept lists   */
+    int64_t reached;
+    int64_t edges_scanned; /* sum of out-degrees of reached vertices          */
+    double  device_ms;
+    /* column (expand) exchange: each front to the R - 1 others of its column */
+    int64_t expand_list_msgs, expand_bitmap_msgs, expand_bytes;
+    int64_t expand_list_only_bytes;   /* the same fronts sent as lists only   */
+    /* row (fold) exchange: each processor to the C - 1 others of its row     */
+    int64_t fold_list_msgs, fold_bitmap_msgs, fold_bytes;
+    int64_t fold_list_only_bytes;     /* the same rows sent as lists only     */
+    int64_t updated;       /* rows accepted by the frontier-update kernel     */
+} bfs_grid2d_stats;
+
+/*
+ * Workspace of a 2D handle (pure host arithmetic).  R, C >= 1 with R * C in
+ * {1, 2, 4} or a multiple of 8 up to 64.  About 8 R V (segment offsets) +
+ * 4 nnz (local rows) + 24 R V (scan of the replicated column fronts) +
+ * 8 C V (predecessor tables and outgoing lists) bytes.
+ * Errors: BFS_ERR_INVALID.
+ */
+int bfs_grid2d_workspace_bytes(int32_t V, int64_t nnz, int32_t R, int32_t C,
+                               size_t *bytes);
+
+/*
+ * Partition a device CSR (as for bfs_graph_create, borrowed for the call
+ * only) into the R x C processors' local matrices, kept in d_workspace
+ * (>= bfs_grid2d_workspace_bytes, 256-byte aligned, borrowed until
+ * destroy).  Offsets and column ids are checked (BFS_ERR_INVALID).
+ * Synchronous.  Errors: BFS_ERR_INVALID, BFS_ERR_WORKSPACE,
+ * BFS_ERR_NO_DEVICE, BFS_ERR_HIP.
+ */
+int bfs_grid2d_create(bfs_grid2d **g, int32_t V, int64_t nnz,
+                      const int64_t *d_row_offsets, const int32_t *d_col,
+                      int32_t R, int32_t C, void *d_workspace, size_t ws_bytes,
+                      void *hip_stream);
+
+/* Release the handle (not the workspace).  NULL is a no-op. */
+int bfs_grid2d_destroy(bfs_grid2d *g);
+
+/*
+ * Single-root search on the processor grid (Algorithm 2).  Outputs and
+ * conventions as bfs_run: d_levels int32[V] (device, written completely),
+ * d_parents int32[V] or NULL; predecessors of vertices found by another
+ * processor are resolved at the end from the finder's table (delayed
+ * predecessor exchange).  msg_mode: BFS_2D_MSG_*.  Synchronous; a handle
+ * runs one search at a time (BFS_ERR_BUSY).
+ */
+int bfs_grid2d_run(bfs_grid2d *g, int32_t root, int32_t msg_mode,
+                   int32_t *d_levels, int32_t *d_parents, void *hip_stream,
+                   bfs_grid2d_stats *st);
+
+/* ---------------------------------------------------------------------- */
 /* Serving: a resident pool of graphs, queries admitted by an HBM budget and
  * batched per graph into multi-source lanes at level boundaries.          */
 

@@ -41,13 +41,18 @@ BFS_OPT_ROW_SKIP = 8
 
 BFS_SRV_NO_PERSISTENT = 0x1
 
+BFS_2D_MSG_AUTO = 0
+BFS_2D_MSG_LIST = 1
+BFS_2D_MSG_BITMAP = 2
+
 # Every symbol include/bfs.h declares.
 EXPORTS = (
     "bfs_last_error", "bfs_version", "bfs_workspace_bytes", "bfs_graph_create",
     "bfs_graph_destroy", "bfs_set_option", "bfs_get_option", "bfs_run", "bfs_run_batch",
     "bfs_server_create", "bfs_server_add_graph", "bfs_submit", "bfs_poll",
     "bfs_server_completed", "bfs_server_get_stats", "bfs_server_drain", "bfs_server_destroy",
-    "bfs_run_noalloc",
+    "bfs_run_noalloc", "bfs_grid2d_workspace_bytes", "bfs_grid2d_create", "bfs_grid2d_destroy",
+    "bfs_grid2d_run",
 )
 
 
@@ -87,6 +92,17 @@ class bfs_server_stats(ctypes.Structure):
                 ("persistent_rounds", ctypes.c_uint64), ("wide_rounds", ctypes.c_uint64)]
 
 
+class bfs_grid2d_stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("list_levels", ctypes.c_int32),
+                ("reached", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
+                ("device_ms", ctypes.c_double),
+                ("expand_list_msgs", ctypes.c_int64), ("expand_bitmap_msgs", ctypes.c_int64),
+                ("expand_bytes", ctypes.c_int64), ("expand_list_only_bytes", ctypes.c_int64),
+                ("fold_list_msgs", ctypes.c_int64), ("fold_bitmap_msgs", ctypes.c_int64),
+                ("fold_bytes", ctypes.c_int64), ("fold_list_only_bytes", ctypes.c_int64),
+                ("updated", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -124,6 +140,12 @@ def load(path: str = LIB_PATH):
         "bfs_server_destroy": (ctypes.c_int, [vp]),
         "bfs_run_noalloc": (ctypes.c_int, [i32, i64, vp, vp, i32, vp, vp, vp,
                                            ctypes.POINTER(bfs_stats)]),
+        "bfs_grid2d_workspace_bytes": (ctypes.c_int, [i32, i64, i32, i32, ctypes.POINTER(sz)]),
+        "bfs_grid2d_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, i64, vp, vp, i32, i32, vp,
+                                             sz, vp]),
+        "bfs_grid2d_destroy": (ctypes.c_int, [vp]),
+        "bfs_grid2d_run": (ctypes.c_int, [vp, i32, i32, vp, vp, vp,
+                                          ctypes.POINTER(bfs_grid2d_stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -207,6 +229,34 @@ def bfs_run_noalloc(V: int, nnz: int, d_row_offsets, d_col, root: int, d_levels,
     st = bfs_stats()
     _check(load().bfs_run_noalloc(V, nnz, _ptr(d_row_offsets), _ptr(d_col), root, _ptr(d_levels),
                                   _ptr(d_parents), _stream(stream), ctypes.byref(st)))
+    return st
+
+
+def bfs_grid2d_workspace_bytes(V: int, nnz: int, R: int, C: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().bfs_grid2d_workspace_bytes(V, nnz, R, C, ctypes.byref(out)))
+    return int(out.value)
+
+
+def bfs_grid2d_create(V: int, nnz: int, d_row_offsets, d_col, R: int, C: int, d_workspace,
+                      ws_bytes: int | None = None, stream=None) -> int:
+    h = ctypes.c_void_p(0)
+    if ws_bytes is None:
+        ws_bytes = d_workspace.numel() * d_workspace.element_size()
+    _check(load().bfs_grid2d_create(ctypes.byref(h), V, nnz, _ptr(d_row_offsets), _ptr(d_col),
+                                    R, C, _ptr(d_workspace), ws_bytes, _stream(stream)))
+    return int(h.value)
+
+
+def bfs_grid2d_destroy(g: int) -> None:
+    _check(load().bfs_grid2d_destroy(g))
+
+
+def bfs_grid2d_run(g: int, root: int, d_levels, d_parents=None, msg_mode: int = BFS_2D_MSG_AUTO,
+                   stream=None) -> bfs_grid2d_stats:
+    st = bfs_grid2d_stats()
+    _check(load().bfs_grid2d_run(g, root, msg_mode, _ptr(d_levels), _ptr(d_parents),
+                                 _stream(stream), ctypes.byref(st)))
     return st
 
 
@@ -336,6 +386,59 @@ class Graph:
     def close(self) -> None:
         if self.handle:
             bfs_graph_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Grid2D:
+    """A CSR partitioned over an R x C grid of virtual processors on one GPU
+    (bfs_grid2d_*).  Owns its workspace tensor; the CSR tensors are needed
+    only while the handle is created."""
+    V: int
+    nnz: int
+    R: int
+    C: int
+    ws: object
+    handle: int
+
+    @classmethod
+    def from_csr(cls, off, col, R: int, C: int, device: str = "cuda", stream=None) -> "Grid2D":
+        import numpy as np
+        import torch
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        V = int(off.shape[0] - 1)
+        nnz = int(off[-1])
+        d_off = torch.from_numpy(off).to(device)
+        d_col = torch.from_numpy(col if col.size else np.zeros(1, np.int32)).to(device)
+        nbytes = bfs_grid2d_workspace_bytes(V, nnz, R, C)
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        torch.cuda.synchronize()
+        h = bfs_grid2d_create(V, nnz, d_off, d_col, R, C, ws, nbytes, stream)
+        torch.cuda.synchronize()
+        del d_off, d_col
+        return cls(V, nnz, R, C, ws, h)
+
+    def run(self, root: int, msg_mode: int = BFS_2D_MSG_AUTO, want_parents: bool = True,
+            levels=None, parents=None, stream=None):
+        import torch
+        dev = self.ws.device
+        if levels is None:
+            levels = torch.empty(self.V, dtype=torch.int32, device=dev)
+        if parents is None and want_parents:
+            parents = torch.empty(self.V, dtype=torch.int32, device=dev)
+        st = bfs_grid2d_run(self.handle, root, levels, parents, msg_mode, stream)
+        return levels, parents, st
+
+    def close(self) -> None:
+        if self.handle:
+            bfs_grid2d_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):
