@@ -26,6 +26,11 @@ carries:
                    its parents through the oracle's validator;
   configs       -- plain single-root searches on R-MAT scales 16 (16 roots)
                    and 22 (64 roots), GTEPS and parity of every root;
+  blocked       -- the same graph and roots on the in-GPU 2D processor grid
+                   (bfs_grid2d_*, Section 2.2 / Algorithm 2) for each R x C
+                   shape asked for: GTEPS, whole-search algorithmic GB/s, the
+                   column and row exchange volumes with list / bitmap
+                   messages against lists only, and every root's parity;
   grid          -- single-root searches on the 4096 x 4096 grid (GTEPS),
                    every root's levels against the Manhattan distance;
   batch         -- 64 roots in one multi-source batch on R-MAT scale 22:
@@ -287,6 +292,64 @@ def single_root(args, torch, np, graphgen, bfsmi):
     return res, g
 
 
+def blocked_section(args, torch, g, roots, bfsmi):
+    """The in-GPU 2D blocked search on the headline graph and roots, one
+    R x C shape at a time: GTEPS (auto message form), the exchange volumes,
+    a lists-only pass for comparison, and every root against the oracle."""
+    from oracle import parallel
+    digest = parallel.csr_digest(g.off, g.col)
+    out = {}
+    for shape in args.blocked.split(","):
+        R, C = (int(x) for x in shape.lower().split("x"))
+        t = time.time()
+        G = bfsmi.Grid2D.from_csr(g.off, g.col, R, C)
+        log("blocked %dx%d: partitioned in %.1fs" % (R, C, time.time() - t))
+        lv = torch.empty(g.V, dtype=torch.int32, device="cuda")
+        pa = torch.empty(g.V, dtype=torch.int32, device="cuda")
+        res = {"R": R, "C": C}
+        for mode, name in ((bfsmi.BFS_2D_MSG_AUTO, "auto"), (bfsmi.BFS_2D_MSG_LIST, "lists_only")):
+            bfsmi.bfs_grid2d_run(G.handle, int(roots[0]), lv, pa, mode)
+            torch.cuda.synchronize()
+            times, stats = [], []
+            for r in roots:
+                t0 = time.perf_counter()
+                st = bfsmi.bfs_grid2d_run(G.handle, int(r), lv, pa, mode)
+                times.append(time.perf_counter() - t0)
+                stats.append(st)
+            summ = search_summary(times, stats, g.V)
+            n = len(stats)
+            summ.update({
+                "expand_msgs_list": sum(x.expand_list_msgs for x in stats) // n,
+                "expand_msgs_bitmap": sum(x.expand_bitmap_msgs for x in stats) // n,
+                "expand_mb": round(sum(x.expand_bytes for x in stats) / n / 1e6, 2),
+                "expand_mb_lists_only": round(sum(x.expand_list_only_bytes for x in stats) / n / 1e6, 2),
+                "fold_msgs_list": sum(x.fold_list_msgs for x in stats) // n,
+                "fold_msgs_bitmap": sum(x.fold_bitmap_msgs for x in stats) // n,
+                "fold_mb": round(sum(x.fold_bytes for x in stats) / n / 1e6, 2),
+                "fold_mb_lists_only": round(sum(x.fold_list_only_bytes for x in stats) / n / 1e6, 2),
+                "updated_per_root": sum(x.updated for x in stats) // n})
+            res[name] = summ
+            log("blocked %dx%d %s: %s" % (R, C, name, summ))
+        ok, nchk = 0, 0
+        for i in range(0, len(roots), 16):
+            items = []
+            for r in roots[i:i + 16]:
+                bfsmi.bfs_grid2d_run(G.handle, int(r), lv, pa, bfsmi.BFS_2D_MSG_AUTO)
+                torch.cuda.synchronize()
+                items.append((int(r), lv.cpu().numpy(), pa.cpu().numpy()))
+            checks = parallel.check_roots(g.off, g.col, items, digest=digest)
+            ok += sum(c.ok for c in checks)
+            nchk += len(checks)
+        res["parity"] = {"roots_checked": nchk, "roots_ok": ok}
+        G.close()
+        del G, lv, pa
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        out["%dx%d" % (R, C)] = res
+    return out
+
+
 def small_config(scale, nroots, args, torch, np, graphgen, bfsmi):
     """Plain single-root searches (levels and parents) on a smaller R-MAT
     graph, every root timed and checked against the oracle."""
@@ -521,6 +584,11 @@ def main():
     ap.add_argument("--no-degree-order", action="store_true")
     ap.add_argument("--summary", type=int, default=-1)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--blocked", default="8x1,2x4",
+                    help="R x C shapes of the 2D blocked search on the headline graph "
+                         "(comma-separated; empty to skip)")
+    ap.add_argument("--blocked-only", action="store_true",
+                    help="generate the headline graph and run only the blocked section")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the scale-16 and scale-22 single-root configurations")
@@ -571,8 +639,18 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
 
+    if args.blocked_only:
+        g = graphgen.rmat(args.scale)
+        roots = graphgen.pick_roots(g, args.roots, graphgen.root_seed(args.scale))
+        print(json.dumps({"blocked": blocked_section(args, torch, g, roots, bfsmi)}), flush=True)
+        return
     res, g = single_root(args, torch, np, graphgen, bfsmi)
     g_V, g_nnz = g.V, g.nnz
+    release()
+    blocked = None
+    if args.blocked:
+        roots = graphgen.pick_roots(g, args.roots, graphgen.root_seed(args.scale))
+        blocked = blocked_section(args, torch, g, roots, bfsmi)
     del g
     release()
     small = {}
@@ -620,6 +698,8 @@ def main():
         out["parity"] = res["parity"]
         if "parity_plain_topdown" in res:
             out["parity_plain_topdown"] = res["parity_plain_topdown"]
+    if blocked is not None:
+        out["blocked"] = blocked
     if small:
         out["configs"] = small
     if grid is not None:

@@ -7,7 +7,10 @@ configuration that bench.py times (degree-ordered graphs, default options).
     validated);
   R-MAT scale 22: all 64 bench roots as single-root searches, and the
     64-root batch;
-  R-MAT scale 16: all 16 bench roots.
+  R-MAT scale 16: all 16 bench roots;
+  the in-GPU 2D blocked search (bfs_grid2d_*) on the scale-26 graph with
+  the bench's 8 x 1 and 2 x 4 processor grids (all 16 roots) and on the
+  scale-22 graph with 1 x 8 and 4 x 4 (all 64 roots).
 Levels are compared with the serial oracle element by element, parents are
 checked by the tree validator, and each search's level / reached / edge
 counts must equal the oracle's.  The oracle runs on a pool of host threads
@@ -28,6 +31,15 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(os.environ.get("BFSMI_BIG", "1") == "0",
                                  reason="full-size graphs disabled (BFSMI_BIG=0)")]
 torch = pytest.importorskip("torch")
+
+
+def blocked_results(G2, roots):
+    out = []
+    for r in roots:
+        lv, pa, st = G2.run(int(r))
+        torch.cuda.synchronize()
+        out.append((int(r), lv.cpu().numpy(), pa.cpu().numpy(), st))
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -57,6 +69,16 @@ def test_rmat26_all_bench_roots(bfsmi):
     assert_parity(g, items, digest=digest, label="rmat26 row skip off")
     del items
     G.close()
+    del G
+    torch.cuda.empty_cache()
+    for R, C in ((8, 1), (2, 4)):
+        G2 = bfsmi.Grid2D.from_csr(g.off, g.col, R, C)
+        items = blocked_results(G2, roots)
+        assert_parity(g, items, digest=digest, label="rmat26 blocked %dx%d" % (R, C))
+        del items
+        G2.close()
+        del G2
+        torch.cuda.empty_cache()
 
 
 def test_grid4096_all_bench_roots(bfsmi):
@@ -95,6 +117,13 @@ def test_rmat22_all_single_roots_and_batch(bfsmi):
     for i, x in enumerate(res):
         assert np.array_equal(got[i].astype(np.int32), x.level), (i, roots[i])
     G.close()
+    del G
+    torch.cuda.empty_cache()
+    for R, C in ((1, 8), (4, 4)):
+        G2 = bfsmi.Grid2D.from_csr(g.off, g.col, R, C)
+        assert_parity(g, blocked_results(G2, roots), digest=digest, comp=comp,
+                      label="rmat22 blocked %dx%d" % (R, C))
+        G2.close()
 
 
 def test_rmat16_all_bench_roots(bfsmi):
