@@ -19,6 +19,10 @@ carries:
                    8 TB/s; the bytes it actually streams are reported beside;
   plain_topdown -- the same searches without the row prefix skip (the plain
                    top-down expansion of Algorithm 3), GTEPS and roofline;
+  direction_optimizing
+                -- the same roots with dense levels searched bottom-up
+                   (BFS_OPT_DIRECTION): GTEPS over the same component edges,
+                   the edges the kernels actually read, parity of every root;
   cpu_baseline  -- the serial CPU oracle on every bench root of the same graph,
                    one search per host thread: all-cores GTEPS and roots/s,
                    the serial time per root, the CPU model and core count;
@@ -260,6 +264,24 @@ def single_root(args, torch, np, graphgen, bfsmi):
         log("plain top-down (row skip off): %s" % plain)
     res["plain_topdown"] = plain
 
+    # the direction-optimizing mode (dense levels bottom-up): the same roots;
+    # TEPS keeps the traversed component's edges as numerator, the edges the
+    # kernels actually read are reported beside it
+    diropt = None
+    if args.direction:
+        G.set_option(bfsmi.BFS_OPT_DIRECTION, 1)
+        bfsmi.bfs_run(G.handle, int(roots[0]), levels, parents)
+        t3, s3, _ = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
+        diropt = search_summary(t3, s3, g.V)
+        diropt["bottom_up_levels_root0"] = s3[0].bottom_up_levels
+        diropt["edges_examined_per_root"] = sum(x.edges_examined for x in s3) // len(s3)
+        diropt["edges_in_component_per_root"] = sum(x.edges_scanned for x in s3) // len(s3)
+        diropt["config"] = {"direction": "optimizing", "alpha": G.get_option(bfsmi.BFS_OPT_DO_ALPHA),
+                            "beta": G.get_option(bfsmi.BFS_OPT_DO_BETA), "degree_order": flags != 0}
+        G.set_option(bfsmi.BFS_OPT_DIRECTION, 0)
+        log("direction-optimizing: %s" % diropt)
+    res["direction_optimizing"] = diropt
+
     if not args.no_cpu_baseline:
         from oracle import parallel
         nthreads = parallel.default_workers(len(roots))
@@ -288,6 +310,12 @@ def single_root(args, torch, np, graphgen, bfsmi):
                 bfsmi, torch, g, G, [int(r) for r in roots], digest,
                 label="rmat%d row skip off" % args.scale)
             G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 1)
+        if diropt is not None:
+            G.set_option(bfsmi.BFS_OPT_DIRECTION, 1)
+            diropt["parity"] = check_against_oracle(
+                bfsmi, torch, g, G, [int(r) for r in roots], digest,
+                label="rmat%d direction-optimizing" % args.scale)
+            G.set_option(bfsmi.BFS_OPT_DIRECTION, 0)
     G.close()
     return res, g
 
@@ -584,6 +612,8 @@ def main():
     ap.add_argument("--no-degree-order", action="store_true")
     ap.add_argument("--summary", type=int, default=-1)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-direction", dest="direction", action="store_false",
+                    help="skip the direction-optimizing twin of the headline")
     ap.add_argument("--blocked", default="8x1,2x4",
                     help="R x C shapes of the 2D blocked search on the headline graph "
                          "(comma-separated; empty to skip)")
@@ -693,6 +723,8 @@ def main():
     }
     if res.get("plain_topdown"):
         out["plain_topdown"] = res["plain_topdown"]
+    if res.get("direction_optimizing"):
+        out["direction_optimizing"] = res["direction_optimizing"]
     if "cpu_baseline" in res:
         out["cpu_baseline"] = res["cpu_baseline"]
         out["parity"] = res["parity"]

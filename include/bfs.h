@@ -96,6 +96,23 @@ extern "C" {
                                       parents are unchanged, edges_scanned
                                       still counts the dropped edges); needs
                                       BFS_OPT_VISITED_SUMMARY >= 1; 0 off    */
+#define BFS_OPT_DIRECTION        9 /* 0 (default) top-down only; 1 direction-
+                                      optimizing: a dense level is searched
+                                      bottom-up (each unvisited vertex looks
+                                      for a visited neighbour, the variant the
+                                      paper's related work discusses), with
+                                      the switches of Beamer et al.: to
+                                      bottom-up when the frontier's edges
+                                      times alpha exceed the unvisited
+                                      vertices' edges, back when the frontier
+                                      times beta is below V and shrinking.
+                                      Levels and valid parents are unchanged;
+                                      fewer edges are examined
+                                      (bfs_stats.edges_examined).  Needs a
+                                      symmetric CSR (checked at creation;
+                                      BFS_ERR_INVALID otherwise)             */
+#define BFS_OPT_DO_ALPHA        10 /* alpha, 1..1000 (default 14)           */
+#define BFS_OPT_DO_BETA         11 /* beta, 1..1000 (default 24)            */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;
@@ -125,6 +142,12 @@ typedef struct bfs_stats {
      * the method reads), + 4 per discovered vertex for its level + 4 more
      * for its parent when parents are requested.                         */
     int64_t expand_alg_bytes;
+    int32_t bottom_up_levels; /* levels searched bottom-up (BFS_OPT_DIRECTION) */
+    int32_t pad0;
+    /* Neighbour ids the search's kernels actually read: the column ids the
+     * top-down expansions streamed (row-skipped edges excluded) plus the
+     * neighbours the bottom-up steps probed.                              */
+    int64_t edges_examined;
 } bfs_stats;
 
 /* Thread-local message of the last failing call ("" if none). */

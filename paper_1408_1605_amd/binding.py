@@ -38,6 +38,9 @@ BFS_OPT_GRID_WGS = 5
 BFS_OPT_PROFILE = 6
 BFS_OPT_VISITED_SUMMARY = 7
 BFS_OPT_ROW_SKIP = 8
+BFS_OPT_DIRECTION = 9
+BFS_OPT_DO_ALPHA = 10
+BFS_OPT_DO_BETA = 11
 
 BFS_SRV_NO_PERSISTENT = 0x1
 
@@ -69,7 +72,8 @@ class bfs_stats(ctypes.Structure):
                 ("scan_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
                 ("compact_ms", ctypes.c_double), ("expand_launches", ctypes.c_int32),
                 ("device_loop_levels", ctypes.c_int32), ("expand_bytes", ctypes.c_int64),
-                ("expand_alg_bytes", ctypes.c_int64)]
+                ("expand_alg_bytes", ctypes.c_int64), ("bottom_up_levels", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("edges_examined", ctypes.c_int64)]
 
 
 class bfs_server_config(ctypes.Structure):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libbfsmi.so")
 ARCH = os.environ.get("BFSMI_ARCH", "gfx950")
 
 SOURCES = ["frontier.hip", "relabel.hip", "rowskip.hip", "msbfs.hip", "smallloop.hip",
-           "msloop.hip", "api.hip", "noalloc.hip", "grid2d.hip", "batch_api.hip", "server.cpp"]
+           "msloop.hip", "api.hip", "noalloc.hip", "grid2d.hip", "bottomup.hip", "batch_api.hip", "server.cpp"]
 
 
 def hipcc() -> str:

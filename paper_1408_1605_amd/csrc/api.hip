@@ -170,7 +170,7 @@ extern "C" {
 
 const char* bfs_last_error(void) { return g_err; }
 
-int bfs_version(void) { return 103; }
+int bfs_version(void) { return 104; }
 
 int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t* bytes)
 {
@@ -283,6 +283,23 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         return cleanup(fail(BFS_ERR_INVALID, "a column id is outside [0, V)"));
     }
     g->maxdeg = h[1];
+    {
+        // symmetry (for the direction-optimizing mode): hash sums of the
+        // edges and of the reversed edges
+        unsigned long long* d_sums = reinterpret_cast<unsigned long long*>(
+            reinterpret_cast<char*>(g->scratch) + 64);
+        unsigned long long hs[4] = {0, 0, 0, 0};
+        e = hipMemcpyAsync(d_sums, hs, sizeof(hs), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_symmetry_sums(s, g->num_cus * 8, V, d_row_offsets, d_col, d_sums);
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, d_sums, sizeof(hs), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipSetDevice(prev);
+            return cleanup(hip_fail(e, "symmetry check"));
+        }
+        g->symmetric = hs[0] == hs[2] && hs[1] == hs[3];
+    }
     if (flags & BFS_DEGREE_ORDER) {
         const int64_t tile_cap = (nnz + kMinTile - 1) / kMinTile + 1;
         int32_t* col_tmp = reinterpret_cast<int32_t*>(g->ws + L.col_tmp);
@@ -357,6 +374,21 @@ int bfs_set_option(bfs_graph* g, int key, int64_t value)
         if (value < 0 || value > 1) return fail(BFS_ERR_INVALID, "row skip must be 0 or 1");
         g->row_skip = (int)value;
         break;
+    case BFS_OPT_DIRECTION:
+        if (value < 0 || value > 1) return fail(BFS_ERR_INVALID, "direction must be 0 or 1");
+        if (value == 1 && !g->symmetric)
+            return fail(BFS_ERR_INVALID,
+                        "direction-optimizing search needs a symmetric CSR (this one is not)");
+        g->direction = (int)value;
+        break;
+    case BFS_OPT_DO_ALPHA:
+        if (value < 1 || value > 1000) return fail(BFS_ERR_INVALID, "alpha must be 1..1000");
+        g->do_alpha = (int)value;
+        break;
+    case BFS_OPT_DO_BETA:
+        if (value < 1 || value > 1000) return fail(BFS_ERR_INVALID, "beta must be 1..1000");
+        g->do_beta = (int)value;
+        break;
     default:
         return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
@@ -375,6 +407,9 @@ int bfs_get_option(bfs_graph* g, int key, int64_t* value)
     case BFS_OPT_PROFILE: *value = g->profile; break;
     case BFS_OPT_VISITED_SUMMARY: *value = g->use_summary; break;
     case BFS_OPT_ROW_SKIP: *value = g->row_skip; break;
+    case BFS_OPT_DIRECTION: *value = g->direction; break;
+    case BFS_OPT_DO_ALPHA: *value = g->do_alpha; break;
+    case BFS_OPT_DO_BETA: *value = g->do_beta; break;
     default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
     return ok();
@@ -460,7 +495,48 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
     int32_t nlevels = 1, bitmap_levels = 0, xlaunches = 0, dev_levels = 0;
     const bool dev_ok = g->loop_driver != 1 && g->small_grid > 0;
     bool dev_left = false;  // the persistent loop just handed a heavy level back
+    // direction-optimizing mode: the degree sum of the frontier a bottom-up
+    // step searches from, and the size of the frontier before it
+    const bool dir_opt = g->direction != 0 && g->symmetric;
+    bool bottom_up = false;
+    int64_t bu_front_deg = 0, bu_prev = 0, examined = 0;
+    int32_t bu_levels = 0;
+    const int nb_grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(((int64_t)g->W + kBitmapWordsPerWG - 1) / kBitmapWordsPerWG, grid_cap));
+    const int sum_grid = std::max(1, std::min(grid_cap, (g->summary_blocks + 31) / 32));
     while (true) {
+        if (bottom_up) {
+            // one bottom-up step discovering depth lvl
+            BFS_HIP_TRY(launch_bottom_up(s, grid_cap, g->V, g->W, g->s_off, g->s_col, g->orig,
+                                         g->vis, g->vis_old, lv_s, pa_s, lvl, g->ctrl, sum_grid,
+                                         g->summary_shift, g->summary_blocks, g->summary));
+            BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+            BFS_HIP_TRY(hipStreamSynchronize(s));
+            const Ctrl& c = *g->h_ctrl;
+            if (c.err) return fail(BFS_ERR_HIP, "internal guard tripped (code %d)", c.err);
+            const int64_t found = c.bu_found;
+            edges += bu_front_deg;  // the searched frontier's vertices are reached ones
+            examined += c.bu_edges;
+            bu_levels++;
+            if (found == 0) break;
+            reached += found;
+            nlevels++;
+            bitmap_levels++;
+            bu_front_deg = c.bu_deg;
+            const bool shrinking = found < bu_prev;
+            bu_prev = found;
+            if (found * g->do_beta < g->V && shrinking) {
+                // back to top-down: the step's vertices (vis & ~vis_old) as
+                // the next queue (the kernel rewrites their level, same value)
+                BFS_HIP_TRY(launch_bitmap_to_queue(s, nb_grid, g->V, g->W, g->vis, g->vis_old,
+                                                   g->q[cur ^ 1], lv_s, lvl, g->ctrl));
+                cur ^= 1;
+                qlen = (int32_t)found;
+                bottom_up = false;
+            }
+            lvl++;
+            continue;
+        }
         if (dev_ok && !dev_left && qlen <= kSmallQ) {
             BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
             BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
@@ -476,6 +552,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
             reached += c.reached;
             nlevels += c.levels;
             edges += c.r_total;
+            examined += c.r_total;
             dev_levels += c.steps;
             cur = (cur + c.steps) & 1;
             lvl = c.level;
@@ -507,6 +584,28 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
                                 g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
                                 g->ctrl, skip_rows ? g->skip : nullptr, g->V));
+        if (dir_opt) {
+            // the frontier's edge count decides the direction (Beamer et
+            // al.): bottom-up when it exceeds the unvisited vertices' edges
+            // divided by alpha; the scan is then not used
+            BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+            BFS_HIP_TRY(hipStreamSynchronize(s));
+            if (g->h_ctrl->err)
+                return fail(BFS_ERR_HIP, "internal guard tripped (code %d)", g->h_ctrl->err);
+            const int64_t mf = g->h_ctrl->r + (skip_rows ? g->h_ctrl->skipped : 0);
+            const int64_t mu = g->nnz - edges - mf;
+            if (mf * g->do_alpha > mu) {
+                if (prof) {
+                    BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
+                    BFS_HIP_TRY(hipEventSynchronize(g->pev[1]));
+                    acc.scan_ms += event_ms(g->pev[0], g->pev[1]);
+                }
+                bottom_up = true;
+                bu_front_deg = mf;
+                bu_prev = qlen;
+                continue;
+            }
+        }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
         BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
                                   g->tile_k, g->s_col, g->summary, lds_sum ? sum_words : 0,
@@ -535,6 +634,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         const uint32_t qn = g->h_ctrl->qn_count;
         const bool bm = g->h_ctrl->bitmap_out != 0;
         edges += r + (skip_rows ? g->h_ctrl->skipped : 0);
+        examined += r;
         xbytes += 4 * r + 20 * (int64_t)qlen + (parents ? 4 : 0) * (int64_t)qn +
                   (bm ? 0 : 8 * (int64_t)qn);
         xalg += 4 * (r + (skip_rows ? g->h_ctrl->skipped : 0)) + (parents ? 8 : 4) * (int64_t)qn;
@@ -573,6 +673,8 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         st->device_loop_levels = dev_levels;
         st->expand_bytes = xbytes;
         st->expand_alg_bytes = xalg;
+        st->bottom_up_levels = bu_levels;
+        st->edges_examined = examined;
     }
     return ok();
 }

@@ -45,6 +45,11 @@ struct alignas(64) Ctrl {
     int64_t skipped;     // edges the degree scan dropped (row prefix skip)
     int32_t fp_cand;     // batch: first id some live lane has not seen (prefix search)
     int32_t pad4;
+    // bottom-up steps (bottomup.hip)
+    uint32_t bu_found;   // vertices found by the step
+    int32_t pad5;
+    int64_t bu_deg;      // their degree sum
+    int64_t bu_edges;    // neighbours the step probed
 };
 
 
@@ -135,6 +140,23 @@ hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W,
 hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,
                          const uint32_t* vis, const int32_t* lvl_int, const int32_t* par_int,
                          int32_t* level, int32_t* parent);
+
+// ---- direction-optimizing search (bottomup.hip) ----
+// One bottom-up step discovering depth lvl: vis_old := vis, the visited
+// summary of that snapshot, then every unvisited vertex takes its first
+// visited neighbour as parent (orig maps it to the caller's id when non-null);
+// new bits go to vis.  Counts land in ctrl->bu_found / bu_deg / bu_edges;
+// ctrl->bitmap_out = 1 and qn_count = 0 so launch_bitmap_to_queue can turn
+// the step's vertices into a queue.
+hipError_t launch_bottom_up(hipStream_t s, int grid, int32_t V, int32_t W, const int64_t* off,
+                            const int32_t* col, const int32_t* orig, uint32_t* vis,
+                            uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
+                            Ctrl* ctrl, int summary_grid, int32_t summary_shift,
+                            int32_t summary_blocks, uint32_t* summary);
+// Wrapping sums of two hashes of every (u, v) and of every (v, u) into
+// sums[0..1] and sums[2..3] (the caller zeroes them).
+hipError_t launch_symmetry_sums(hipStream_t s, int grid, int32_t V, const int64_t* off,
+                                const int32_t* col, unsigned long long* sums);
 
 // ---- multi-source batch (msbfs.hip) ----
 // The two masks of a vertex that the expansion tests together.

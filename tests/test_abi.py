@@ -148,7 +148,7 @@ def test_binding_structs_match_header(tmp_path):
     if gcc is None:
         pytest.skip("no gcc")
     structs = [binding.bfs_stats, binding.bfs_server_config, binding.bfs_timing,
-               binding.bfs_server_stats]
+               binding.bfs_server_stats, binding.bfs_grid2d_stats]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bfs.h"', 'int main(void) {']
     for S in structs:
         n = S.__name__

@@ -8,6 +8,8 @@ configuration that bench.py times (degree-ordered graphs, default options).
   R-MAT scale 22: all 64 bench roots as single-root searches, and the
     64-root batch;
   R-MAT scale 16: all 16 bench roots;
+  the direction-optimizing mode on all 16 scale-26 and all 64 scale-22
+  roots;
   the in-GPU 2D blocked search (bfs_grid2d_*) on the scale-26 graph with
   the bench's 8 x 1 and 2 x 4 processor grids (all 16 roots) and on the
   scale-22 graph with 1 x 8 and 4 x 4 (all 64 roots).
@@ -71,6 +73,16 @@ def test_rmat26_all_bench_roots(bfsmi):
     G.close()
     del G
     torch.cuda.empty_cache()
+    # direction-optimizing searches (bottom-up dense levels) of the same roots
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_DIRECTION, 1)
+    items = gpu_results(torch, G, roots)
+    assert all(st.bottom_up_levels > 0 for _, _, _, st in items)
+    assert_parity(g, items, digest=digest, label="rmat26 direction-optimizing")
+    del items
+    G.close()
+    del G
+    torch.cuda.empty_cache()
     for R, C in ((8, 1), (2, 4)):
         G2 = bfsmi.Grid2D.from_csr(g.off, g.col, R, C)
         items = blocked_results(G2, roots)
@@ -110,6 +122,10 @@ def test_rmat22_all_single_roots_and_batch(bfsmi):
     items = gpu_results(torch, G, roots)
     assert_parity(g, items, digest=digest, comp=comp, label="rmat22 single roots")
     del items
+    G.set_option(bfsmi.BFS_OPT_DIRECTION, 1)
+    assert_parity(g, gpu_results(torch, G, roots), digest=digest, comp=comp,
+                  label="rmat22 direction-optimizing")
+    G.set_option(bfsmi.BFS_OPT_DIRECTION, 0)
     out, st = G.run_batch(roots)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
