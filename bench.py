@@ -204,18 +204,52 @@ def single_root(args, torch, np, graphgen, bfsmi):
     log("uploaded and created graph handle (flags %d) in %.1fs" % (flags, time.time() - t))
     if args.summary >= 0:
         G.set_option(bfsmi.BFS_OPT_VISITED_SUMMARY, args.summary)
+
+    # the CPU oracle on every bench root (the cpu_baseline figures; its
+    # levels also gate the autotuner's candidates and check the GPU results)
+    from oracle import parallel
+    nthreads = parallel.default_workers(len(roots))
+    digest = parallel.csr_digest(g.off, g.col, nthreads)
+    ref_levels = []
+    if not args.no_cpu_baseline:
+        log("cpu baseline: serial oracle, %d roots on %d host threads ..." % (len(roots), nthreads))
+        ref, wall, used = parallel.bfs_roots(g.off, g.col, [int(r) for r in roots],
+                                             workers=nthreads, fresh=True, digest=digest)
+        serial = [x.seconds for x in ref]
+        edges = sum(x.edges_scanned for x in ref)
+        cpu_baseline = {
+            "value": round(edges / 2 / wall / 1e9, 5), "unit": "GTEPS", "cores": used,
+            "kind": "oracle",
+            "sample": "the %d bench roots of the same R-MAT scale %d graph, one serial oracle "
+                      "search per host thread, %.1f s wall" % (len(roots), args.scale, wall),
+            "roots_per_s_all_cores": round(len(roots) / wall, 4),
+            "serial_s_per_root": round(sum(serial) / len(serial), 3),
+            "serial_gteps": round(harmonic_mean([x.edges_scanned / 2 / x.seconds / 1e9
+                                                 for x in ref]), 5),
+            "cpu": cpu_model(), "nproc": os.cpu_count()}
+        ref_levels = [x.level for x in ref[:args.tune_roots]]
+        del ref
+
+    # autotuned launch knobs, every candidate gated on the oracle's levels
     tuned = None
-    if args.autotune:
+    if args.autotune and ref_levels:
         from paper_1408_1605_amd import autotune
-        tuned = autotune.load_cached("rmat", args.scale)
+        cls = "rmat_do" if not args.no_degree_order else "rmat"
+        tuned = autotune.load_cached(cls, args.scale)
+        troots = [int(r) for r in roots[:len(ref_levels)]]
         if tuned is None:
-            best, table = autotune.tune_single(G, [int(r) for r in roots[:4]], log=log)
-            tuned = dict(best or {})
-            autotune.save("rmat", args.scale, {"single": tuned, "table": table})
-        else:
-            tuned = tuned.get("single", {})
-        autotune.apply(G, tuned)
+            t = time.time()
+            best, table = autotune.tune_single(G, troots, ref_levels, log=log)
+            dbest, dtable = autotune.tune_direction(G, troots, ref_levels, log=log)
+            tuned = {"single": best, "direction": dbest,
+                     "candidates": len(table) + len(dtable),
+                     "failed_parity": sum(not x["parity"] for x in table + dtable),
+                     "tuning_s": round(time.time() - t, 1)}
+            autotune.save(cls, args.scale, tuned)
+        autotune.apply(G, {k: v for k, v in (tuned.get("single") or {}).items()
+                           if k in autotune.SINGLE_SPACE})
         log("autotuned configuration: %s" % tuned)
+    del ref_levels
     if args.ept:
         G.set_option(bfsmi.BFS_OPT_EDGES_PER_THREAD, args.ept)
     G.set_option(bfsmi.BFS_OPT_PROFILE, 0)
@@ -269,6 +303,10 @@ def single_root(args, torch, np, graphgen, bfsmi):
     # kernels actually read are reported beside it
     diropt = None
     if args.direction:
+        if tuned and tuned.get("direction"):
+            from paper_1408_1605_amd import autotune
+            autotune.apply(G, {k: v for k, v in tuned["direction"].items()
+                               if k in autotune.DIRECTION_SPACE})
         G.set_option(bfsmi.BFS_OPT_DIRECTION, 1)
         bfsmi.bfs_run(G.handle, int(roots[0]), levels, parents)
         t3, s3, _ = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
@@ -282,26 +320,9 @@ def single_root(args, torch, np, graphgen, bfsmi):
         log("direction-optimizing: %s" % diropt)
     res["direction_optimizing"] = diropt
 
+    res["tuned"] = tuned
     if not args.no_cpu_baseline:
-        from oracle import parallel
-        nthreads = parallel.default_workers(len(roots))
-        digest = parallel.csr_digest(g.off, g.col, nthreads)
-        log("cpu baseline: serial oracle, %d roots on %d host threads ..." % (len(roots), nthreads))
-        ref, wall, used = parallel.bfs_roots(g.off, g.col, [int(r) for r in roots],
-                                             workers=nthreads, fresh=True, digest=digest)
-        serial = [x.seconds for x in ref]
-        edges = sum(x.edges_scanned for x in ref)
-        res["cpu_baseline"] = {
-            "value": round(edges / 2 / wall / 1e9, 5), "unit": "GTEPS", "cores": used,
-            "kind": "oracle",
-            "sample": "the %d bench roots of the same R-MAT scale %d graph, one serial oracle "
-                      "search per host thread, %.1f s wall" % (len(roots), args.scale, wall),
-            "roots_per_s_all_cores": round(len(roots) / wall, 4),
-            "serial_s_per_root": round(sum(serial) / len(serial), 3),
-            "serial_gteps": round(harmonic_mean([x.edges_scanned / 2 / x.seconds / 1e9
-                                                 for x in ref]), 5),
-            "cpu": cpu_model(), "nproc": os.cpu_count()}
-        del ref
+        res["cpu_baseline"] = cpu_baseline
         res["parity"] = check_against_oracle(bfsmi, torch, g, G, [int(r) for r in roots],
                                              digest, label="rmat%d default" % args.scale)
         if plain is not None:
@@ -454,6 +475,23 @@ def batch_section(args, torch, np, graphgen, bfsmi):
     G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_WS_BATCH | bfsmi.BFS_DEGREE_ORDER)
     out = torch.empty((64, g.V), dtype=torch.int8, device="cuda")
     lv = torch.empty(g.V, dtype=torch.int32, device="cuda")
+    # the oracle's rows (the scale-22 single-root section has usually cached
+    # these roots already): they gate the tile autotuner and check the result
+    from oracle import parallel
+    ref, _, _ = parallel.bfs_roots(g.off, g.col, roots)
+    rows_ref = np.stack([x.level.astype(np.int8) for x in ref])
+    del ref
+    tuned = None
+    if args.autotune:
+        from paper_1408_1605_amd import autotune
+        tuned = autotune.load_cached("rmat_batch", scale)
+        if tuned is None:
+            best, table = autotune.tune_batch(G, roots, rows_ref, log=log)
+            tuned = {"batch": best, "candidates": len(table),
+                     "failed_parity": sum(not x["parity"] for x in table)}
+            autotune.save("rmat_batch", scale, tuned)
+        autotune.apply(G, tuned.get("batch") or {})
+        log("batch tile: %d" % G.get_option(bfsmi.BFS_OPT_BATCH_TILE))
     for _ in range(2):
         bfsmi.bfs_run_batch(G.handle, roots, out)
     torch.cuda.synchronize()
@@ -470,17 +508,16 @@ def batch_section(args, torch, np, graphgen, bfsmi):
         bfsmi.bfs_run(G.handle, r, lv, None)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    # every row against the oracle (the scale-22 single-root section has
-    # usually cached these roots already)
-    from oracle import parallel
+    # every row against the oracle
     rows = out.cpu().numpy()
-    ref, _, _ = parallel.bfs_roots(g.off, g.col, roots)
-    ok = sum(bool(np.array_equal(rows[i].astype(np.int32), x.level)) for i, x in enumerate(ref))
+    ok = sum(bool(np.array_equal(rows[i], rows_ref[i])) for i in range(len(roots)))
+    tile = G.get_option(bfsmi.BFS_OPT_BATCH_TILE)
     G.close()
     res = {"graph": "rmat%d" % scale, "n_roots": 64, "batch_ms": round(t_batch * 1e3, 3),
            "roots_per_s": round(64 / t_batch, 1), "sequential_roots_per_s": round(64 / t_seq, 1),
            "speedup_vs_sequential": round(t_seq / t_batch, 2), "union_levels": st.levels,
-           "union_edges_scanned": st.edges_scanned,
+           "union_edges_scanned": st.edges_scanned, "batch_tile": tile,
+           "tuned": tuned,
            "parity": {"rows_checked": len(roots), "rows_ok": int(ok)}}
     log("batch: %s" % res)
     return res
@@ -611,7 +648,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-degree-order", action="store_true")
     ap.add_argument("--summary", type=int, default=-1)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default launch knobs (no oracle-gated tuning)")
+    ap.add_argument("--tune-roots", type=int, default=4,
+                    help="bench roots whose oracle levels gate the tuning candidates")
     ap.add_argument("--no-direction", dest="direction", action="store_false",
                     help="skip the direction-optimizing twin of the headline")
     ap.add_argument("--blocked", default="8x1,2x4",
@@ -715,6 +755,7 @@ def main():
                    "roots": args.roots, "levels_root0": res["levels"],
                    "reached_root0": res["reached"], "edges_scanned_root0": res["edges_scanned"]},
         "roofline": res["roofline"],
+        "tuned": res.get("tuned"),
         "median_gteps": res["median_gteps"],
         "bfs_alg_gbs": res["bfs_alg_gbs"],
         "bfs_roofline_frac": res["bfs_roofline_frac"],

@@ -113,6 +113,9 @@ extern "C" {
                                       BFS_ERR_INVALID otherwise)             */
 #define BFS_OPT_DO_ALPHA        10 /* alpha, 1..1000 (default 14)           */
 #define BFS_OPT_DO_BETA         11 /* beta, 1..1000 (default 24)            */
+#define BFS_OPT_LOOP_LIMIT      12 /* largest frontier (vertices) the
+                                      persistent small-level loop takes and
+                                      keeps: 64..65536 (default 65536)     */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;

@@ -1,12 +1,19 @@
 """Autotuner for the search's launch knobs.
 
-Knobs: edges per thread (tile size), the visited-summary mode and
-workgroups per CU for the single-root path, and the tile size of the batch
-expansion.  Every candidate is first checked for parity: its levels (and
-batch rows) must equal those of a reference configuration (list frontier,
-one edge per thread, no summary) on the same roots, which the GPU tests pin
-to the CPU oracle; only then is it timed.  The best configuration is cached
-as JSON per (GPU architecture, graph class, scale).
+Spaces:
+  single    -- edges per thread (the expansion's tile: 256 * EPT edges), the
+               visited-summary mode, workgroups per CU, and the largest
+               frontier the persistent small-level loop runs;
+  direction -- the alpha / beta switch thresholds of the direction-optimizing
+               mode;
+  batch     -- the multi-source batch's tile (edges per workgroup).
+
+Every candidate is run on the tuning roots first and its levels are compared
+element by element with expected levels that the caller supplies (the CPU
+oracle's, computed outside this package); a candidate that differs is
+recorded as failing parity and never timed.  Of the passing candidates the
+fastest (mean wall time per search over `reps` rounds) is chosen.  Results
+are cached as JSON per (GPU architecture, graph class, scale).
 """
 from __future__ import annotations
 
@@ -17,6 +24,16 @@ import time
 from . import binding as B
 
 CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
+
+SINGLE_SPACE = {"ept": (1, 2, 4, 8), "summary": (1, 2), "grid_wgs": (4, 8),
+                "loop_limit": (4096, 16384, 65536)}
+DIRECTION_SPACE = {"alpha": (4, 8, 14, 24, 48), "beta": (8, 24, 72)}
+BATCH_SPACE = {"batch_tile": (256, 512, 1024, 2048)}
+
+_OPT = {"ept": B.BFS_OPT_EDGES_PER_THREAD, "summary": B.BFS_OPT_VISITED_SUMMARY,
+        "grid_wgs": B.BFS_OPT_GRID_WGS, "loop_limit": B.BFS_OPT_LOOP_LIMIT,
+        "alpha": B.BFS_OPT_DO_ALPHA, "beta": B.BFS_OPT_DO_BETA,
+        "batch_tile": B.BFS_OPT_BATCH_TILE, "direction": B.BFS_OPT_DIRECTION}
 
 
 def _arch() -> str:
@@ -29,84 +46,94 @@ def cache_path(graph_class: str, scale: int) -> str:
     return os.path.join(CACHE_DIR, "%s_%s_%d.json" % (_arch(), graph_class, scale))
 
 
-def _levels(G, root, lv):
-    import torch
-    B.bfs_run(G.handle, root, lv, None)
-    torch.cuda.synchronize()
-    return lv.clone()
+def _grid(space: dict):
+    keys = list(space)
+    out = [{}]
+    for k in keys:
+        out = [dict(c, **{k: v}) for c in out for v in space[k]]
+    return out
 
 
-def tune_single(G, roots, reps: int = 3, log=None):
-    """Returns (best_config, table).  G is a binding.Graph."""
+def _to_device(expected, dtype):
+    import numpy as np
     import torch
-    lv = torch.empty(G.V, dtype=torch.int32, device="cuda")
-    saved = {k: B.bfs_get_option(G.handle, k) for k in
-             (B.BFS_OPT_EDGES_PER_THREAD, B.BFS_OPT_VISITED_SUMMARY, B.BFS_OPT_FRONTIER_MODE,
-              B.BFS_OPT_GRID_WGS)}
-    # reference outputs
-    B.bfs_set_option(G.handle, B.BFS_OPT_EDGES_PER_THREAD, 1)
-    B.bfs_set_option(G.handle, B.BFS_OPT_VISITED_SUMMARY, 0)
-    B.bfs_set_option(G.handle, B.BFS_OPT_FRONTIER_MODE, 1)
-    ref = [_levels(G, r, lv) for r in roots]
-    B.bfs_set_option(G.handle, B.BFS_OPT_FRONTIER_MODE, 0)
+    return [torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).cuda() for x in expected]
+
+
+def _tune(G, cands, run_one, outputs, expected_dev, reps, log, tag):
+    """Shared loop: set each candidate, gate on parity, then time it."""
+    import torch
+    saved = {k: B.bfs_get_option(G.handle, _OPT[k]) for k in cands[0]}
     table = []
-    for ept in (1, 2, 4, 8):
-        for summ in (0, 1, 2):
-            for wgs in (4, 8):
-                B.bfs_set_option(G.handle, B.BFS_OPT_EDGES_PER_THREAD, ept)
-                B.bfs_set_option(G.handle, B.BFS_OPT_VISITED_SUMMARY, summ)
-                B.bfs_set_option(G.handle, B.BFS_OPT_GRID_WGS, wgs)
-                ok = all(bool(torch.equal(_levels(G, r, lv), x)) for r, x in zip(roots, ref))
-                ms = None
-                if ok:
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    for _ in range(reps):
-                        for r in roots:
-                            B.bfs_run(G.handle, r, lv, None)
-                    torch.cuda.synchronize()
-                    ms = (time.perf_counter() - t0) * 1e3 / (reps * len(roots))
-                row = {"ept": ept, "summary": summ, "grid_wgs": wgs, "parity": ok, "ms": ms}
-                table.append(row)
-                if log:
-                    log("tune single %s" % row)
-    for k, v in saved.items():
-        B.bfs_set_option(G.handle, k, v)
-    good = [t for t in table if t["parity"]]
-    best = min(good, key=lambda t: t["ms"]) if good else None
-    return best, table
-
-
-def tune_batch(G, roots, reps: int = 2, log=None):
-    """Batch tile size; G must have been created with BFS_WS_BATCH."""
-    import torch
-    out = torch.empty((len(roots), G.V), dtype=torch.int8, device="cuda")
-    saved = B.bfs_get_option(G.handle, B.BFS_OPT_BATCH_TILE)
-    B.bfs_set_option(G.handle, B.BFS_OPT_BATCH_TILE, 256)
-    B.bfs_run_batch(G.handle, roots, out)
-    torch.cuda.synchronize()
-    ref = out.clone()
-    table = []
-    for tile in (256, 512, 1024, 2048):
-        B.bfs_set_option(G.handle, B.BFS_OPT_BATCH_TILE, tile)
-        B.bfs_run_batch(G.handle, roots, out)
-        torch.cuda.synchronize()
-        ok = bool(torch.equal(out, ref))
+    for c in cands:
+        for k, v in c.items():
+            B.bfs_set_option(G.handle, _OPT[k], int(v))
+        ok = True
+        for i, out in enumerate(outputs()):
+            run_one(i)
+            torch.cuda.synchronize()
+            ok = ok and bool(torch.equal(out, expected_dev[i]))
         ms = None
         if ok:
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
-                B.bfs_run_batch(G.handle, roots, out)
+                for i in range(len(expected_dev)):
+                    run_one(i)
             torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / reps
-        row = {"batch_tile": tile, "parity": ok, "ms": ms}
+            ms = (time.perf_counter() - t0) * 1e3 / (reps * len(expected_dev))
+        row = dict(c, parity=ok, ms=ms)
         table.append(row)
         if log:
-            log("tune batch %s" % row)
-    B.bfs_set_option(G.handle, B.BFS_OPT_BATCH_TILE, saved)
+            log("tune %s %s" % (tag, row))
+    for k, v in saved.items():
+        B.bfs_set_option(G.handle, _OPT[k], v)
     good = [t for t in table if t["parity"]]
     best = min(good, key=lambda t: t["ms"]) if good else None
     return best, table
+
+
+def tune_single(G, roots, expected, reps: int = 2, log=None, space: dict | None = None):
+    """Single-root knobs.  expected[i]: int32 levels of roots[i] (the oracle's).
+    Returns (best_config or None, table)."""
+    import torch
+    lv = torch.empty(G.V, dtype=torch.int32, device="cuda")
+    exp = _to_device(expected, "int32")
+    roots = [int(r) for r in roots]
+
+    def outputs():
+        for _ in roots:
+            yield lv
+
+    return _tune(G, _grid(space or SINGLE_SPACE), lambda i: B.bfs_run(G.handle, roots[i], lv, None),
+                 outputs, exp, reps, log, "single")
+
+
+def tune_direction(G, roots, expected, reps: int = 2, log=None, space: dict | None = None):
+    """alpha / beta of the direction-optimizing mode (switched on here and
+    restored afterwards)."""
+    saved = B.bfs_get_option(G.handle, B.BFS_OPT_DIRECTION)
+    B.bfs_set_option(G.handle, B.BFS_OPT_DIRECTION, 1)
+    try:
+        return tune_single(G, roots, expected, reps, log, space or DIRECTION_SPACE)
+    finally:
+        B.bfs_set_option(G.handle, B.BFS_OPT_DIRECTION, saved)
+
+
+def tune_batch(G, roots, expected_rows, reps: int = 2, log=None, space: dict | None = None):
+    """Batch tile; G must have been created with BFS_WS_BATCH.
+    expected_rows: int8 [len(roots)][V] (the oracle's levels per root)."""
+    import numpy as np
+    import torch
+    out = torch.empty((len(roots), G.V), dtype=torch.int8, device="cuda")
+    exp = _to_device([np.asarray(expected_rows)], "int8")
+    roots = [int(r) for r in roots]
+
+    def outputs():
+        yield out
+
+    return _tune(G, _grid(space or BATCH_SPACE), lambda i: B.bfs_run_batch(G.handle, roots, out),
+                 outputs, exp, reps, log, "batch")
 
 
 def save(graph_class: str, scale: int, result: dict) -> str:
@@ -126,14 +153,7 @@ def load_cached(graph_class: str, scale: int):
 
 
 def apply(G, cfg: dict) -> None:
-    """Set a tuned single-root configuration on a graph handle."""
-    if not cfg:
-        return
-    if "ept" in cfg:
-        B.bfs_set_option(G.handle, B.BFS_OPT_EDGES_PER_THREAD, int(cfg["ept"]))
-    if "summary" in cfg:
-        B.bfs_set_option(G.handle, B.BFS_OPT_VISITED_SUMMARY, int(cfg["summary"]))
-    if "grid_wgs" in cfg:
-        B.bfs_set_option(G.handle, B.BFS_OPT_GRID_WGS, int(cfg["grid_wgs"]))
-    if "batch_tile" in cfg:
-        B.bfs_set_option(G.handle, B.BFS_OPT_BATCH_TILE, int(cfg["batch_tile"]))
+    """Set a tuned configuration (any of the tuned knobs) on a graph handle."""
+    for k, v in (cfg or {}).items():
+        if k in _OPT and k != "direction":
+            B.bfs_set_option(G.handle, _OPT[k], int(v))

@@ -374,6 +374,11 @@ int bfs_set_option(bfs_graph* g, int key, int64_t value)
         if (value < 0 || value > 1) return fail(BFS_ERR_INVALID, "row skip must be 0 or 1");
         g->row_skip = (int)value;
         break;
+    case BFS_OPT_LOOP_LIMIT:
+        if (value < 64 || value > kSmallQ)
+            return fail(BFS_ERR_INVALID, "loop limit must be 64..%d", kSmallQ);
+        g->small_limit = (int32_t)value;
+        break;
     case BFS_OPT_DIRECTION:
         if (value < 0 || value > 1) return fail(BFS_ERR_INVALID, "direction must be 0 or 1");
         if (value == 1 && !g->symmetric)
@@ -408,6 +413,7 @@ int bfs_get_option(bfs_graph* g, int key, int64_t* value)
     case BFS_OPT_VISITED_SUMMARY: *value = g->use_summary; break;
     case BFS_OPT_ROW_SKIP: *value = g->row_skip; break;
     case BFS_OPT_DIRECTION: *value = g->direction; break;
+    case BFS_OPT_LOOP_LIMIT: *value = g->small_limit; break;
     case BFS_OPT_DO_ALPHA: *value = g->do_alpha; break;
     case BFS_OPT_DO_BETA: *value = g->do_beta; break;
     default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
@@ -537,13 +543,13 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
             lvl++;
             continue;
         }
-        if (dev_ok && !dev_left && qlen <= kSmallQ) {
+        if (dev_ok && !dev_left && qlen <= g->small_limit) {
             BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
             BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
             BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
                                             g->vis, g->vis_old, g->q[cur], g->q[cur ^ 1], lv_s,
                                             pa_s, g->small_sync, g->small_side, g->ctrl, qlen,
-                                            lvl, kSmallQ,
+                                            lvl, g->small_limit,
                                             (int64_t)g->small_grid * kSmallDeg, kSmallDeg));
             BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
             BFS_HIP_TRY(hipStreamSynchronize(s));

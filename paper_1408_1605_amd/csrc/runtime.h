@@ -96,6 +96,7 @@ struct bfs_graph {
     int profile = 0;
     int use_summary = 1;
     int row_skip = 1;
+    int32_t small_limit = 1 << 16;  // largest frontier the persistent loop runs (<= 65536)
     int direction = 0;      // 1: direction-optimizing (bottom-up steps on dense levels)
     int do_alpha = 14;      // top-down -> bottom-up when frontier edges * alpha > unvisited edges
     int do_beta = 24;       // bottom-up -> top-down when frontier * beta < V and shrinking
