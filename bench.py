@@ -93,7 +93,11 @@ def kernel_source_hash():
     for f in ("frontier.hip", "tile_map.h", "wave_ops.h", "bfs_internal.h", "relabel.hip",
               "rowskip.hip"):
         with open(os.path.join(ROOT, "paper_1408_1605_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        if f == "bfs_internal.h":
+            # its constants and the control block, not the launcher declarations
+            text = text.split(b"// ---- single-root kernels", 1)[0]
+        h.update(text)
     return h.hexdigest()[:16]
 
 
@@ -284,7 +288,7 @@ def single_root(args, torch, np, graphgen, bfsmi):
 
     # the plain top-down expansion of Algorithm 3 (no row prefix skip)
     plain = None
-    if not args.no_degree_order:
+    if not args.no_degree_order and args.plain:
         G.set_option(bfsmi.BFS_OPT_ROW_SKIP, 0)
         bfsmi.bfs_run(G.handle, int(roots[0]), levels, parents)
         t2, s2, tot2 = timed_pass(bfsmi, G, roots, levels, parents, len(roots))
@@ -652,6 +656,8 @@ def main():
                     help="keep the default launch knobs (no oracle-gated tuning)")
     ap.add_argument("--tune-roots", type=int, default=4,
                     help="bench roots whose oracle levels gate the tuning candidates")
+    ap.add_argument("--no-plain", dest="plain", action="store_false",
+                    help="skip the plain top-down twin of the headline")
     ap.add_argument("--no-direction", dest="direction", action="store_false",
                     help="skip the direction-optimizing twin of the headline")
     ap.add_argument("--blocked", default="8x1,2x4",

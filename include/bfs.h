@@ -84,9 +84,9 @@ extern "C" {
 #define BFS_OPT_VISITED_SUMMARY  7 /* before heavy levels, summarise the visited
                                       bitmap so the expansion's early visited
                                       test skips most bitmap loads:
-                                      0 off, 1 (default) fully visited id
-                                      prefix, 2 prefix + one LDS bit per fully
-                                      visited block of ids                    */
+                                      0 off, 1 fully visited id prefix,
+                                      2 (default) prefix + one LDS bit per
+                                      fully visited block of ids              */
 #define BFS_OPT_ROW_SKIP         8 /* degree-ordered graphs: 1 (default) lets a
                                       heavy level's degree scan drop each
                                       frontier row's leading block of edges

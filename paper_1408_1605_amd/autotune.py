@@ -93,7 +93,8 @@ def _tune(G, cands, run_one, outputs, expected_dev, reps, log, tag):
     return best, table
 
 
-def tune_single(G, roots, expected, reps: int = 2, log=None, space: dict | None = None):
+def tune_single(G, roots, expected, reps: int = 2, log=None, space: dict | None = None,
+                tag: str = "single"):
     """Single-root knobs.  expected[i]: int32 levels of roots[i] (the oracle's).
     Returns (best_config or None, table)."""
     import torch
@@ -106,7 +107,7 @@ def tune_single(G, roots, expected, reps: int = 2, log=None, space: dict | None 
             yield lv
 
     return _tune(G, _grid(space or SINGLE_SPACE), lambda i: B.bfs_run(G.handle, roots[i], lv, None),
-                 outputs, exp, reps, log, "single")
+                 outputs, exp, reps, log, tag)
 
 
 def tune_direction(G, roots, expected, reps: int = 2, log=None, space: dict | None = None):
@@ -115,7 +116,7 @@ def tune_direction(G, roots, expected, reps: int = 2, log=None, space: dict | No
     saved = B.bfs_get_option(G.handle, B.BFS_OPT_DIRECTION)
     B.bfs_set_option(G.handle, B.BFS_OPT_DIRECTION, 1)
     try:
-        return tune_single(G, roots, expected, reps, log, space or DIRECTION_SPACE)
+        return tune_single(G, roots, expected, reps, log, space or DIRECTION_SPACE, "direction")
     finally:
         B.bfs_set_option(G.handle, B.BFS_OPT_DIRECTION, saved)
 

@@ -311,11 +311,20 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         if (e == hipSuccess)
             e = build_row_skip(s, V, g->s_off, col_tmp, const_cast<int32_t*>(g->s_col), g->skip,
                                g->num_cus * 8);
+        // internal ids run in non-increasing degree class, so the vertices
+        // with a neighbour are exactly the ids below their count
+        uint32_t* d_cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->scratch) + 128);
+        uint32_t h_cnt = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(d_cnt, &h_cnt, 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_count_nonzero_degree(s, g->num_cus * 8, V, g->s_off, d_cnt);
+        if (e == hipSuccess) e = hipMemcpyAsync(&h_cnt, d_cnt, 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             (void)hipSetDevice(prev);
             return cleanup(hip_fail(e, "degree ordering"));
         }
+        g->v_active = (int32_t)h_cnt;
     }
     (void)hipSetDevice(prev);
     *out = g;
@@ -513,9 +522,10 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
     while (true) {
         if (bottom_up) {
             // one bottom-up step discovering depth lvl
-            BFS_HIP_TRY(launch_bottom_up(s, grid_cap, g->V, g->W, g->s_off, g->s_col, g->orig,
-                                         g->vis, g->vis_old, lv_s, pa_s, lvl, g->ctrl, sum_grid,
-                                         g->summary_shift, g->summary_blocks, g->summary));
+            BFS_HIP_TRY(launch_bottom_up(s, grid_cap, g->V, g->rank ? g->v_active : g->V, g->W,
+                                         g->s_off, g->s_col, g->orig, g->vis, g->vis_old, lv_s,
+                                         pa_s, lvl, g->ctrl, sum_grid, g->summary_shift,
+                                         g->summary_blocks, g->summary));
             BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
             BFS_HIP_TRY(hipStreamSynchronize(s));
             const Ctrl& c = *g->h_ctrl;

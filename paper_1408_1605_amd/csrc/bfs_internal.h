@@ -148,11 +148,16 @@ hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank
 // new bits go to vis.  Counts land in ctrl->bu_found / bu_deg / bu_edges;
 // ctrl->bitmap_out = 1 and qn_count = 0 so launch_bitmap_to_queue can turn
 // the step's vertices into a queue.
-hipError_t launch_bottom_up(hipStream_t s, int grid, int32_t V, int32_t W, const int64_t* off,
-                            const int32_t* col, const int32_t* orig, uint32_t* vis,
-                            uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
-                            Ctrl* ctrl, int summary_grid, int32_t summary_shift,
+// Only ids below V_scan are candidates (ids at or above it have no
+// neighbour; V_scan = V when that is not known).
+hipError_t launch_bottom_up(hipStream_t s, int grid, int32_t V, int32_t V_scan, int32_t W,
+                            const int64_t* off, const int32_t* col, const int32_t* orig,
+                            uint32_t* vis, uint32_t* vis_old, int32_t* level, int32_t* parent,
+                            int32_t lvl, Ctrl* ctrl, int summary_grid, int32_t summary_shift,
                             int32_t summary_blocks, uint32_t* summary);
+// Adds the number of vertices with a neighbour to *out.
+hipError_t launch_count_nonzero_degree(hipStream_t s, int grid, int32_t V, const int64_t* off,
+                                       uint32_t* out);
 // Wrapping sums of two hashes of every (u, v) and of every (v, u) into
 // sums[0..1] and sums[2..3] (the caller zeroes them).
 hipError_t launch_symmetry_sums(hipStream_t s, int grid, int32_t V, const int64_t* off,

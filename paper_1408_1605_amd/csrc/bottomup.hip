@@ -3,7 +3,8 @@
 // vertices, each looking for one neighbour in the frontier, instead of from
 // the frontier's edges), and the symmetry check that guards it.
 //
-// A bottom-up step for depth lvl runs over every vertex id.  An unvisited
+// A bottom-up step for depth lvl runs over every vertex id that has a
+// neighbour (under degree order the ids below the count of such vertices).  An unvisited
 // vertex scans its row in stored order and stops at the first neighbour that
 // was visited when the step began; that neighbour is its parent.  At the
 // start of the step the visited set is exactly the vertices of depth
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kWG) void k_bu_begin(int32_t W, const uint32_t* __r
 }
 
 // One wave per 64 consecutive vertex ids (two bitmap words).
-__global__ __launch_bounds__(kWG) void k_bottom_up(int32_t V, int32_t W,
+__global__ __launch_bounds__(kWG) void k_bottom_up(int32_t V, int32_t V_scan, int32_t W,
                                                    const int64_t* __restrict__ off,
                                                    const int32_t* __restrict__ col,
                                                    const int32_t* __restrict__ orig,
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kWG) void k_bottom_up(int32_t V, int32_t W,
     constexpr int U = 4;  // neighbours probed together
     const int lane = __lane_id();
     const int32_t fp = ctrl->full_prefix;
-    const int64_t nunits = ((int64_t)V + 63) / 64;
+    const int64_t nunits = ((int64_t)V_scan + 63) / 64;
     const int64_t nwaves = (int64_t)gridDim.x * (kWG / 64);
     uint32_t found_n = 0;
     int64_t found_deg = 0, examined = 0;
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kWG) void k_bottom_up(int32_t V, int32_t W,
         const int64_t v = unit * 64 + lane;
         const int64_t w0 = unit * 2;
         bool visited = true;
-        if (v < V) visited = (snap[v >> 5] >> (v & 31)) & 1u;
+        if (v < V_scan) visited = (snap[v >> 5] >> (v & 31)) & 1u;
         int32_t par = -1;
         int64_t deg = 0;
         if (!visited) {
@@ -116,10 +117,33 @@ __global__ __launch_bounds__(kWG) void k_bottom_up(int32_t V, int32_t W,
     }
 }
 
-hipError_t launch_bottom_up(hipStream_t s, int grid, int32_t V, int32_t W, const int64_t* off,
-                            const int32_t* col, const int32_t* orig, uint32_t* vis,
-                            uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
-                            Ctrl* ctrl, int summary_grid, int32_t summary_shift,
+// Vertices with at least one neighbour (creation time: under degree order
+// they are exactly the internal ids below the count, so a bottom-up step
+// need not look at the rest, which no search can reach).
+__global__ __launch_bounds__(kWG) void k_count_nonzero_degree(int32_t V,
+                                                              const int64_t* __restrict__ off,
+                                                              uint32_t* __restrict__ out)
+{
+    uint32_t n = 0;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < V; v += stride)
+        n += off[v + 1] > off[v] ? 1u : 0u;
+    for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
+    if (__lane_id() == 0 && n) atomicAdd(out, n);
+}
+
+hipError_t launch_count_nonzero_degree(hipStream_t s, int grid, int32_t V, const int64_t* off,
+                                       uint32_t* out)
+{
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_count_nonzero_degree, dim3(grid), dim3(kWG), 0, s, V, off, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bottom_up(hipStream_t s, int grid, int32_t V, int32_t V_scan, int32_t W,
+                            const int64_t* off, const int32_t* col, const int32_t* orig,
+                            uint32_t* vis, uint32_t* vis_old, int32_t* level, int32_t* parent,
+                            int32_t lvl, Ctrl* ctrl, int summary_grid, int32_t summary_shift,
                             int32_t summary_blocks, uint32_t* summary)
 {
     if (grid < 1) grid = 1;
@@ -129,10 +153,11 @@ hipError_t launch_bottom_up(hipStream_t s, int grid, int32_t V, int32_t W, const
     hipError_t e = launch_visited_summary(s, summary_grid, V, W, vis_old, summary_shift,
                                           summary_blocks, summary, ctrl);
     if (e != hipSuccess) return e;
-    const int64_t units = ((int64_t)V + 63) / 64;
+    if (V_scan < 0 || V_scan > V) V_scan = V;
+    const int64_t units = ((int64_t)V_scan + 63) / 64;
     const int64_t bgrid = std::min<int64_t>(grid, (units + 3) / 4);
     hipLaunchKernelGGL(k_bottom_up, dim3((unsigned)std::max<int64_t>(bgrid, 1)), dim3(kWG), 0, s,
-                       V, W, off, col, orig, vis, vis_old, level, parent, lvl, ctrl);
+                       V, V_scan, W, off, col, orig, vis, vis_old, level, parent, lvl, ctrl);
     return hipGetLastError();
 }
 

@@ -529,9 +529,11 @@ __global__ __launch_bounds__(kWG) void k2_expand(const Plan* __restrict__ plp,
 // message is the sender's list when the sender kept one and it is not
 // longer than the block's bitmap (Section 5), else the sender's bitmap words
 // of block m that turned on this level.  An unvisited received row is
-// claimed with atomicOr in the receiver's bitmap; the winner sets its level,
-// records the sender's column as its predecessor (-2 - column) and, in list
-// mode, appends it to the receiver's next front.
+// claimed with atomicOr in the receiver's bitmap (a bitmap message claims a
+// whole word at once: sender and receiver number the block's rows alike);
+// the winner sets its level, records the sender's column as its predecessor
+// (-2 - column) and, in list mode, appends it to the receiver's next front
+// (one reservation per wave).
 
 __device__ __forceinline__ bool fold_is_list(const Plan& pl, const Ctl* ctl, int32_t p, int32_t m)
 {
@@ -552,6 +554,7 @@ __global__ __launch_bounds__(kWG) void k2_update(const Plan* __restrict__ plp,
     const int32_t R = pl.R, C = pl.C, B = pl.B, WB = pl.WB, lvl = pl.lvl;
     const SlotWork sw = slot_work(pl);
     const int64_t pw = (int64_t)C * WB;  // bitmap words per processor
+    const int64_t step = (int64_t)sw.nw * kWG;
     uint32_t accepted = 0, carried = 0;
     for (int32_t t = sw.first; t < sw.end; ++t) {
         const int32_t q = pl.porder[t];
@@ -560,40 +563,82 @@ __global__ __launch_bounds__(kWG) void k2_update(const Plan* __restrict__ plp,
         int32_t* prq = pred + (int64_t)q * C * B;
         const bool qlist = ctl->listmode[q] != 0;
         int32_t* qfront = dst + ((int64_t)q * C + m) * B;
+        uint32_t* qcnt = &ctl->dcnt[q * C + m];
         const int64_t vbase = (int64_t)(m * R + i) * B - (int64_t)m * B;  // v = vbase + r
-        auto take = [&](int32_t r, int32_t jj) {
-            const uint32_t bit = 1u << (r & 31);
-            if (bmq[r >> 5] & bit) return;
-            const uint32_t o = atomicOr(bmq + (r >> 5), bit);
-            if (o & bit) return;
-            level[vbase + r] = lvl;
-            prq[r] = -2 - jj;
-            accepted++;
-            if (qlist) {
-                const uint32_t pos = atomicAdd(&ctl->dcnt[q * C + m], 1u);
-                if (pos < (uint32_t)B) qfront[pos] = i * B + (r - m * B);
-                else ctl->err = 3;
-            }
-        };
+        const int32_t cbase = i * B - m * B;                              // ROW2COL(r) = cbase + r
         for (int32_t jj = 0; jj < C; ++jj) {
             if (jj == m) continue;
             const int32_t p = jj * R + i;
             if (fold_is_list(pl, ctl, p, m)) {
-                const uint32_t n = ctl->dcnt[p * C + m];
+                // list message: one row per thread, one claim each; the
+                // workgroup walks the list in uniform steps so a wave's
+                // winners append with one reservation
+                const int64_t n = ctl->dcnt[p * C + m];
                 const int32_t* src = dst + ((int64_t)p * C + m) * B;
-                for (int64_t e = (int64_t)sw.widx * kWG + threadIdx.x; e < n;
-                     e += (int64_t)sw.nw * kWG)
-                    take(src[e], jj);
+                for (int64_t e0 = (int64_t)sw.widx * kWG; e0 < n; e0 += step) {
+                    const int64_t e = e0 + threadIdx.x;
+                    bool win = false;
+                    int32_t r = 0;
+                    if (e < n) {
+                        r = src[e];
+                        const uint32_t bit = 1u << (r & 31);
+                        if (!(bmq[r >> 5] & bit)) win = !(atomicOr(bmq + (r >> 5), bit) & bit);
+                    }
+                    if (win) {
+                        level[vbase + r] = lvl;
+                        prq[r] = -2 - jj;
+                        accepted++;
+                    }
+                    if (qlist) {
+                        const uint64_t mask = __ballot(win);
+                        uint32_t base = 0;
+                        if (__lane_id() == 0 && mask) base = atomicAdd(qcnt, (uint32_t)__popcll(mask));
+                        base = __shfl(base, 0, 64);
+                        if (win) {
+                            const uint32_t pos = base + lanes_below(mask);
+                            if (pos < (uint32_t)B) qfront[pos] = cbase + r;
+                            else ctl->err = 3;
+                        }
+                    }
+                }
             } else {
+                // bitmap message: the sender's words of block m that turned on
+                // this level; sender and receiver number the block's rows the
+                // same way, so a word is claimed with one atomicOr
                 const uint32_t* a = bm + (int64_t)p * pw + (int64_t)m * WB;
                 const uint32_t* b = bm_old + (int64_t)p * pw + (int64_t)m * WB;
-                for (int64_t w = (int64_t)sw.widx * kWG + threadIdx.x; w < WB;
-                     w += (int64_t)sw.nw * kWG) {
-                    uint32_t f = a[w] & ~b[w];
-                    carried += __popc(f);
-                    while (f) {
-                        take(m * B + (int32_t)w * 32 + __builtin_ctz(f), jj);
-                        f &= f - 1;
+                uint32_t* rq = bmq + (int64_t)m * WB;
+                for (int64_t w0 = (int64_t)sw.widx * kWG; w0 < WB; w0 += step) {
+                    const int64_t w = w0 + threadIdx.x;
+                    uint32_t got = 0;
+                    if (w < WB) {
+                        const uint32_t f = a[w] & ~b[w];
+                        carried += __popc(f);
+                        const uint32_t open = f & ~rq[w];
+                        if (open) got = open & ~atomicOr(rq + w, open);
+                    }
+                    const uint32_t ng = (uint32_t)__popc(got);
+                    accepted += ng;
+                    uint32_t at = 0;
+                    if (qlist) {
+                        // wave-wide prefix of the new rows, one reservation per wave
+                        const uint32_t incl = wave_inclusive_scan<uint32_t>(ng);
+                        uint32_t base = 0;
+                        const uint32_t tot = __shfl(incl, 63, 64);
+                        if (__lane_id() == 63 && tot) base = atomicAdd(qcnt, tot);
+                        at = __shfl(base, 63, 64) + incl - ng;
+                    }
+                    const int32_t r0 = m * B + (int32_t)w * 32;
+                    while (got) {
+                        const int32_t r = r0 + __builtin_ctz(got);
+                        got &= got - 1;
+                        level[vbase + r] = lvl;
+                        prq[r] = -2 - jj;
+                        if (qlist) {
+                            if (at < (uint32_t)B) qfront[at] = cbase + r;
+                            else ctl->err = 3;
+                            at++;
+                        }
                     }
                 }
             }

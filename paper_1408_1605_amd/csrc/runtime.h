@@ -94,13 +94,14 @@ struct bfs_graph {
     int batch_tile = 1024;  // edges per workgroup in the batch expansion
     int grid_wgs = 8;
     int profile = 0;
-    int use_summary = 1;
+    int use_summary = 2;
     int row_skip = 1;
     int32_t small_limit = 1 << 16;  // largest frontier the persistent loop runs (<= 65536)
     int direction = 0;      // 1: direction-optimizing (bottom-up steps on dense levels)
     int do_alpha = 14;      // top-down -> bottom-up when frontier edges * alpha > unvisited edges
     int do_beta = 24;       // bottom-up -> top-down when frontier * beta < V and shrinking
     int symmetric = 0;      // the CSR equals its transpose (checked at creation)
+    int32_t v_active = 0;   // degree order: internal ids below it have a neighbour (else V)
 
     std::atomic<int> busy{0};
 };

@@ -174,6 +174,8 @@ struct SrvGraph {
     SrvBatch* batch = nullptr;     // worker thread only
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev = nullptr;  // round start / end (timing events)
+    hipEvent_t ev_stage = nullptr;  // after staging copies that no round event follows
+    bool stage_pending = false;     // ev_stage recorded and not yet seen complete
     Ctrl* h_ctrl = nullptr;        // pinned
     int16_t** h_lane_out = nullptr;  // pinned staging for the lane table
     int32_t* h_join = nullptr;     // pinned staging for joins
@@ -522,7 +524,8 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
         bad |= launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->sn, P.clear) != hipSuccess;
     for (int i = 0; i < P.n_join; ++i)
         bad |= launch_fill16(G.stream, g->num_cus * 2, P.fill[i], g->V, (int16_t)-1) != hipSuccess;
-    if (P.n_join || P.table)
+    const bool staged = P.n_join || P.table;
+    if (staged)
         bad |= hipMemcpyAsync(B->lane_out, G.h_lane_out, 64 * sizeof(int16_t*),
                               hipMemcpyHostToDevice, G.stream) != hipSuccess;
     if (P.n_join) {
@@ -531,8 +534,15 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
         bad |= launch_srv_join(G.stream, g->V, P.n_join, B->join, g->rank, B->sn, B->front,
                                B->lane_out, B->lane_start, B->q[B->parity], B->ctrl) != hipSuccess;
     }
+    if (staged && P.round < 0 && !P.release) {
+        // no round event follows these copies: the pinned staging they read
+        // must not be rewritten (next plan_step) before the stream has read it
+        bad |= hipEventRecord(G.ev_stage, G.stream) != hipSuccess;
+        G.stage_pending = true;
+    }
     if (P.release) {
         drop_batch_device(G);
+        G.stage_pending = false;  // the stream was synchronised
         {
             std::lock_guard<std::mutex> lk(mu);
             arena.release(B->mem);
@@ -567,6 +577,12 @@ bool bfs_server::step_graph(SrvGraph& G)
     SrvBatch* B = G.batch;
     bool round_done = false, round_err = false;
     double round_ms = 0.0;
+    if (G.stage_pending) {
+        const hipError_t q = hipEventQuery(G.ev_stage);
+        if (q == hipErrorNotReady) return false;
+        if (q != hipSuccess) set_err(BFS_ERR_HIP);
+        G.stage_pending = false;
+    }
     if (B && B->in_flight) {
         const hipError_t q = hipEventQuery(G.ev);
         if (q == hipErrorNotReady) return false;
@@ -685,6 +701,7 @@ int bfs_server_add_graph(bfs_server* s, bfs_graph* g, int32_t* graph_id)
     hipError_t e = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&G.ev0);
     if (e == hipSuccess) e = hipEventCreate(&G.ev);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&G.ev_stage, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&G.h_ctrl, sizeof(Ctrl) + 64 * sizeof(int16_t*) + 128 * sizeof(int32_t),
                           hipHostMallocDefault);
@@ -706,6 +723,7 @@ int bfs_server_add_graph(bfs_server* s, bfs_graph* g, int32_t* graph_id)
         if (G.stream) (void)hipStreamDestroy(G.stream);
         if (G.ev0) (void)hipEventDestroy(G.ev0);
         if (G.ev) (void)hipEventDestroy(G.ev);
+        if (G.ev_stage) (void)hipEventDestroy(G.ev_stage);
         if (G.h_ctrl) (void)hipHostFree(G.h_ctrl);
         return hip_fail(e, "server graph resources");
     }
@@ -874,6 +892,7 @@ int bfs_server_destroy(bfs_server* s)
         if (G.stream) (void)hipStreamDestroy(G.stream);
         if (G.ev0) (void)hipEventDestroy(G.ev0);
         if (G.ev) (void)hipEventDestroy(G.ev);
+        if (G.ev_stage) (void)hipEventDestroy(G.ev_stage);
         if (G.h_ctrl) (void)hipHostFree(G.h_ctrl);
     }
     if (s->poll_stream) (void)hipStreamDestroy(s->poll_stream);
