@@ -104,8 +104,10 @@ extern "C" {
                                       the switches of Beamer et al.: to
                                       bottom-up when the frontier's edges
                                       times alpha exceed the unvisited
-                                      vertices' edges, back when the frontier
-                                      times beta is below V and shrinking.
+                                      vertices' edges (while the frontier
+                                      grows), back for good when the
+                                      frontier times beta is below V and
+                                      shrinking.
                                       Levels and valid parents are unchanged;
                                       fewer edges are examined
                                       (bfs_stats.edges_examined).  Needs a

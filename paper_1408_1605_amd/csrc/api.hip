@@ -514,6 +514,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
     // step searches from, and the size of the frontier before it
     const bool dir_opt = g->direction != 0 && g->symmetric;
     bool bottom_up = false;
+    bool bu_done = false;  // the search has switched back from bottom-up
     int64_t bu_front_deg = 0, bu_prev = 0, examined = 0;
     int32_t bu_levels = 0;
     const int nb_grid = (int)std::max<int64_t>(
@@ -549,6 +550,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
                 cur ^= 1;
                 qlen = (int32_t)found;
                 bottom_up = false;
+                bu_done = true;  // the frontier shrinks from here on: stay top-down
             }
             lvl++;
             continue;
@@ -600,7 +602,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
                                 g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
                                 g->ctrl, skip_rows ? g->skip : nullptr, g->V));
-        if (dir_opt) {
+        if (dir_opt && !bu_done) {
             // the frontier's edge count decides the direction (Beamer et
             // al.): bottom-up when it exceeds the unvisited vertices' edges
             // divided by alpha; the scan is then not used
@@ -633,8 +635,10 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         if (maybe_bitmap) {
             const int64_t nb = ((int64_t)g->W + kBitmapWordsPerWG - 1) / kBitmapWordsPerWG;
             const int grid2 = (int)std::max<int64_t>(1, std::min<int64_t>(nb, grid_cap));
+            // the direction-optimizing mode also sums the next frontier's
+            // degrees, so the next level's direction is known without a scan
             BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->vis, g->vis_old, Qn, lv_s,
-                                               lvl, g->ctrl));
+                                               lvl, g->ctrl, dir_opt ? g->s_off : nullptr));
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
         BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -661,6 +665,16 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         qlen = (int32_t)qn;
         cur ^= 1;
         lvl++;
+        if (dir_opt && bm && !bu_done) {
+            // the compaction summed the new frontier's degrees: decide its
+            // level's direction now (Beamer et al.'s test)
+            const int64_t mf = g->h_ctrl->next_deg;
+            if (mf * g->do_alpha > g->nnz - edges - mf) {
+                bottom_up = true;
+                bu_front_deg = mf;
+                bu_prev = qlen;
+            }
+        }
     }
     if (g->rank) {
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));

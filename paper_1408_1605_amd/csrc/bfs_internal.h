@@ -15,6 +15,8 @@ constexpr int kMinTile = kWG;         // smallest edge tile (EPT = 1)
 constexpr int kSummaryMaxWords = 2048; // visited summary: <= 8 KB of LDS
 constexpr int kSkipLow = 16;          // row prefix skip thresholds 2^(16 + i) ...
 constexpr int kSkipLevels = 10;       // ... for i = 0..9
+constexpr int kBigTiles = 16;         // scan: an entry spanning this many tiles or more ...
+constexpr int kBigTileList = 256;     // ... is queued (up to this many per block) for the workgroup
 
 // Per-level control block in device memory.  The host reads it back once
 // per level; the kernels read the fields they need directly.
@@ -50,6 +52,7 @@ struct alignas(64) Ctrl {
     int32_t pad5;
     int64_t bu_deg;      // their degree sum
     int64_t bu_edges;    // neighbours the step probed
+    int64_t next_deg;    // degree sum of the next frontier, when the bitmap compaction is asked for it
 };
 
 
@@ -132,9 +135,11 @@ hipError_t launch_visited_summary(hipStream_t s, int grid, int32_t V, int32_t W,
 // Resident expansion workgroups per CU for this configuration.
 int expand_blocks_per_cu(int ept, int summary_words);
 
+// deg_off non-null: also adds the degrees of the new frontier's vertices
+// (from these row offsets) to ctrl->next_deg.
 hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
                                   uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
-                                  Ctrl* ctrl);
+                                  Ctrl* ctrl, const int64_t* deg_off = nullptr);
 
 // Degree order: caller-ordered outputs from the internal-id ones.
 hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kWG) void k_bu_begin(int32_t W, const uint32_t* __r
         ctrl->bu_found = 0;
         ctrl->bu_deg = 0;
         ctrl->bu_edges = 0;
+        ctrl->next_deg = 0;
     }
 }
 

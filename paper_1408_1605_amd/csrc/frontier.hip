@@ -212,6 +212,7 @@ __global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, in
         ctrl->qlen = qlen;
         ctrl->bitmap_out = (allow_bitmap == 2 && r > 0) || (allow_bitmap == 1 && r > bitmap_threshold);
         ctrl->qn_count = 0;
+        ctrl->next_deg = 0;
         ctrl->r_total += r;
         cumul[qlen] = r;
         tile_k[ntiles] = qlen - 1;
@@ -229,6 +230,11 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
     // +1 word of padding every 8 entries keeps the strided reads conflict-light
     __shared__ int32_t s_deg[kScanChunk + kScanChunk / kScanItems];
     __shared__ int64_t s_cum[kScanChunk];  // transposes the stores
+    // entries whose edges cover many tiles (hubs) have their tile heads
+    // written by the whole workgroup instead of by their own thread
+    __shared__ int64_t s_big_t0[kBigTileList], s_big_t1[kBigTileList];
+    __shared__ int32_t s_big_k[kBigTileList];
+    __shared__ int32_t s_nbig;
     if (dev && ctrl->done) return;
     const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
     const int64_t nblk = ((int64_t)qlen + kScanChunk - 1) / kScanChunk;
@@ -249,8 +255,9 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
             local[j] = sum;
             sum += s_deg[li + li / kScanItems];
         }
+        if (threadIdx.x == 0) s_nbig = 0;
         int64_t tot;
-        const int64_t ex = wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
+        const int64_t ex = wg_exclusive_scan<int64_t>(sum, &tot, s_wave);  // barriers inside
         const int64_t start = bsum[blk] + ex;
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
@@ -264,11 +271,27 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
                     const int64_t t0 = (c + tile - 1) / tile;
                     int64_t t1 = (c + d - 1) / tile;
                     if (t1 >= tile_cap) t1 = tile_cap - 1;
-                    for (int64_t t = t0; t <= t1; ++t) tile_k[t] = (int32_t)k;
+                    bool mine = true;
+                    if (t1 - t0 >= kBigTiles) {
+                        const int32_t slot = atomicAdd(&s_nbig, 1);
+                        if (slot < kBigTileList) {
+                            s_big_t0[slot] = t0;
+                            s_big_t1[slot] = t1;
+                            s_big_k[slot] = (int32_t)k;
+                            mine = false;
+                        }
+                    }
+                    if (mine)
+                        for (int64_t t = t0; t <= t1; ++t) tile_k[t] = (int32_t)k;
                 }
             }
         }
         __syncthreads();
+        const int32_t nbig = min(s_nbig, kBigTileList);
+        for (int32_t b = 0; b < nbig; ++b) {
+            const int32_t k = s_big_k[b];
+            for (int64_t t = s_big_t0[b] + threadIdx.x; t <= s_big_t1[b]; t += kWG) tile_k[t] = k;
+        }
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
             const int32_t li = j * kWG + threadIdx.x;
@@ -589,13 +612,15 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
                                                          uint32_t* __restrict__ vis_old,
                                                          int32_t* __restrict__ Qn,
                                                          int32_t* __restrict__ level,
-                                                         int32_t lvl, Ctrl* __restrict__ ctrl)
+                                                         int32_t lvl, Ctrl* __restrict__ ctrl,
+                                                         const int64_t* __restrict__ deg_off)
 {
     if (!ctrl->bitmap_out) return;
     __shared__ uint32_t s_f[kBitmapWordsPerWG];
     __shared__ uint32_t s_off[kBitmapWordsPerWG];
     __shared__ uint32_t s_wave[kWG / 64];
     __shared__ uint32_t s_base;
+    int64_t dsum = 0;  // degrees of the new vertices this thread wrote
     const int64_t nblocks = ((int64_t)W + kBitmapWordsPerWG - 1) / kBitmapWordsPerWG;
     for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
         const int64_t i = blk * kBitmapWordsPerWG + threadIdx.x;
@@ -626,20 +651,26 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
                     if (base + rank < (uint32_t)V) Qn[base + rank] = v;
                     else ctrl->err = 3;
                     level[v] = lvl;
+                    if (deg_off) dsum += deg_off[v + 1] - deg_off[v];
                 }
             }
         }
         __syncthreads();
     }
+    if (deg_off) {
+        for (int d = 32; d >= 1; d >>= 1) dsum += __shfl_xor(dsum, d, 64);
+        if (__lane_id() == 0 && dsum)
+            atomicAdd((unsigned long long*)&ctrl->next_deg, (unsigned long long)dsum);
+    }
 }
 
 hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
                                   uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
-                                  Ctrl* ctrl)
+                                  Ctrl* ctrl, const int64_t* deg_off)
 {
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid), dim3(kWG), 0, s, V, W, vis, vis_old, Qn,
-                       level, lvl, ctrl);
+                       level, lvl, ctrl, deg_off);
     return hipGetLastError();
 }
 
