@@ -57,6 +57,12 @@ import platform
 import sys
 import time
 
+# The serving section drives one stream per resident graph; HIP maps a
+# process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default), and
+# with 4 a deep graph's rounds wait behind other graphs' kernels.  Set before
+# anything starts HIP.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -674,6 +680,8 @@ def main():
     ap.add_argument("--batch-scale", type=int, default=22)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving section")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-arena-gb", type=int, default=16)
@@ -715,6 +723,9 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
 
+    if args.serve_only:
+        print(json.dumps({"serve": serve_section(args, torch, np, graphgen, bfsmi)}), flush=True)
+        return
     if args.blocked_only:
         g = graphgen.rmat(args.scale)
         roots = graphgen.pick_roots(g, args.roots, graphgen.root_seed(args.scale))

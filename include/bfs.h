@@ -163,7 +163,10 @@ int bfs_version(void);
 
 /*
  * Device workspace needed by a graph with V vertices and nnz directed CSR
- * entries.  Pure host arithmetic: never touches the device.
+ * entries: the per-search arrays of Section 3.1 (visited bitmap of
+ * ceil(V/32) words, frontier queues, level and predecessor by search id)
+ * and the degree scan of Section 3.4.  Pure host arithmetic: never touches
+ * the device.
  *   V    : 1 .. 2^31 - 1;  nnz : 0 .. 2^62
  *   flags: BFS_WS_BATCH adds the batch arrays (3 * 8 * V bytes, and 64 * V
  *   more with BFS_DEGREE_ORDER: the batch rows by internal id).
@@ -172,7 +175,11 @@ int bfs_version(void);
 int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t *bytes);
 
 /*
- * Create a graph handle over a CSR that is already in device memory.
+ * Create a graph handle over a CSR that is already in device memory.  The
+ * CSR row of u lists u's out-neighbours, i.e. the paper's CSC column of u
+ * (Section 3.1); creation-time work (checks, the degree-ordered relabel and
+ * row grouping) stands where the paper partitions the graph before timing
+ * starts (Section 4).
  *   d_row_offsets: int64[V + 1], d_row_offsets[0] = 0, non-decreasing,
  *                  d_row_offsets[V] = nnz (device, borrowed)
  *   d_col        : int32[nnz] neighbour ids in [0, V) (device, borrowed)
@@ -197,7 +204,11 @@ int bfs_set_option(bfs_graph *g, int key, int64_t value);
 int bfs_get_option(bfs_graph *g, int key, int64_t *value);
 
 /*
- * Single-root search.
+ * Single-root search: the level loop of Algorithm 2 on one processor, each
+ * level the degree scan and edge -> thread map of Section 3.4 (multi-edge
+ * threads, Section 3.4.1), the claim of Algorithm 3 and the list / bitmap
+ * frontier of Section 5; Algorithm 2's initialisation fixes the outputs'
+ * conventions.
  *   root     : 0 <= root < V
  *   d_levels : int32[V] (device, caller-owned), written completely
  *   d_parents: int32[V] (device) or NULL to skip predecessors
@@ -211,7 +222,8 @@ int bfs_run(bfs_graph *g, int32_t root, int32_t *d_levels, int32_t *d_parents,
 /*
  * Multi-source batch: n_roots independent searches run together, one bit of
  * a 64-bit mask per root and vertex, the union frontier expanded once per
- * level.  Needs a graph created with BFS_WS_BATCH.
+ * level with the scan and edge -> thread map of Section 3.4; each lane's
+ * levels are those of its own single-root search (Algorithm 2).  Needs a graph created with BFS_WS_BATCH.
  *   h_roots : int32[n_roots] (host), each in [0, V); repeats are allowed
  *   n_roots : 1 .. 64
  *   d_levels: int8[n_roots][V] (device, row-major by root), written
@@ -347,6 +359,9 @@ typedef struct bfs_timing {
 /*
  * Create a server over a caller-owned device arena of arena_bytes (the HBM
  * budget for per-graph batch state and per-query outputs).  cfg nullable.
+ * Each query's result is its own single-root search's levels (Algorithm 2);
+ * the server batches queries of one graph as lanes of bfs_run_batch's
+ * multi-source search.
  */
 int bfs_server_create(bfs_server **s, void *d_arena, size_t arena_bytes,
                       const bfs_server_config *cfg);

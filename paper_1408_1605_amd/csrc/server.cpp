@@ -23,6 +23,13 @@
 //
 // The worker takes the server lock only to move queries and arena blocks;
 // its HIP calls run unlocked, so submit/poll never wait behind a launch.
+//
+// Every graph has its own stream, and HIP maps a process's streams onto a
+// few hardware queues (GPU_MAX_HW_QUEUES, 4 by default): a deep graph's
+// round then waits behind other graphs' kernels in its queue.  Serving
+// processes run with 8 hardware queues (the benchmark sets it before HIP
+// starts); that, with the persistent rounds' wider limits, roughly halves
+// the deep graphs' time per level in a mixed pool.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -163,8 +170,8 @@ constexpr int32_t kSmallV = 1 << 16;                // graphs this small: contin
 // together), and the level sizes they take.
 constexpr int kMsGrid = 32;
 constexpr int kMaxPersist = 8;
-constexpr int32_t kMsQLimit = 1 << 16;
-constexpr int64_t kMsRLimit = 1 << 18;
+constexpr int32_t kMsQLimit = 1 << 17;
+constexpr int64_t kMsRLimit = 1 << 19;
 constexpr int32_t kMsDLimit = 8192;
 
 struct SrvGraph {
