@@ -118,6 +118,21 @@ extern "C" {
 #define BFS_OPT_LOOP_LIMIT      12 /* largest frontier (vertices) the
                                       persistent small-level loop takes and
                                       keeps: 64..65536 (default 65536)     */
+#define BFS_OPT_CLAIM_MODE      13 /* degree-ordered graphs: how a level whose
+                                      next frontier takes the bitmap form
+                                      records the vertices it finds.  0: the
+                                      atomicOr claim on the visited bitmap of
+                                      Algorithm 3; 2: each vertex found gets a
+                                      byte flag (a plain byte store, read
+                                      first; no atomics) and a parent from
+                                      the frontier, and the flags become
+                                      bitmap bits when the frontier is
+                                      compacted; 1 (default): 2 when V is at
+                                      most 2^24 (flags of at most 16 MiB),
+                                      else 0.  Levels whose next frontier is
+                                      a list always claim with atomicOr.
+                                      Every mode gives the same levels and
+                                      valid parents                          */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;

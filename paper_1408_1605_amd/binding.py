@@ -42,6 +42,7 @@ BFS_OPT_DIRECTION = 9
 BFS_OPT_DO_ALPHA = 10
 BFS_OPT_DO_BETA = 11
 BFS_OPT_LOOP_LIMIT = 12
+BFS_OPT_CLAIM_MODE = 13
 
 BFS_SRV_NO_PERSISTENT = 0x1
 

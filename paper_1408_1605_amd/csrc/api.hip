@@ -92,6 +92,7 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
         L.lvl_int = take((size_t)V * 4);
         L.par_int = take((size_t)V * 4);
         if (flags & BFS_WS_BATCH) L.ms_out = take((size_t)64 * V);  // batch rows by internal id
+        L.found = take(W * 32);  // flag claims: one byte per id, padded to whole words
     }
     L.total = p;
     return L;
@@ -152,6 +153,7 @@ void bind_workspace(bfs_graph* g, char* ws, const WsLayout& L, uint32_t flags)
         g->lvl_int = reinterpret_cast<int32_t*>(ws + L.lvl_int);
         g->par_int = reinterpret_cast<int32_t*>(ws + L.par_int);
         if (flags & BFS_WS_BATCH) g->ms_out = reinterpret_cast<int8_t*>(ws + L.ms_out);
+        g->found = reinterpret_cast<uint8_t*>(ws + L.found);
     }
     if (flags & BFS_WS_BATCH) {
         g->ms_sn = reinterpret_cast<SeenNext*>(ws + L.ms_sn);
@@ -170,7 +172,7 @@ extern "C" {
 
 const char* bfs_last_error(void) { return g_err; }
 
-int bfs_version(void) { return 104; }
+int bfs_version(void) { return 105; }
 
 int bfs_workspace_bytes(int32_t V, int64_t nnz, uint32_t flags, size_t* bytes)
 {
@@ -403,6 +405,10 @@ int bfs_set_option(bfs_graph* g, int key, int64_t value)
         if (value < 1 || value > 1000) return fail(BFS_ERR_INVALID, "beta must be 1..1000");
         g->do_beta = (int)value;
         break;
+    case BFS_OPT_CLAIM_MODE:
+        if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "claim mode must be 0..2");
+        g->claim_mode = (int)value;
+        break;
     default:
         return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
@@ -425,6 +431,7 @@ int bfs_get_option(bfs_graph* g, int key, int64_t* value)
     case BFS_OPT_LOOP_LIMIT: *value = g->small_limit; break;
     case BFS_OPT_DO_ALPHA: *value = g->do_alpha; break;
     case BFS_OPT_DO_BETA: *value = g->do_beta; break;
+    case BFS_OPT_CLAIM_MODE: *value = g->claim_mode; break;
     default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
     return ok();
@@ -495,8 +502,12 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
     int32_t* lv_s = g->rank ? g->lvl_int : levels;
     int32_t* pa_s = parents ? (g->rank ? g->par_int : parents) : nullptr;
     if (timed) BFS_HIP_TRY(hipEventRecord(g->ev0, s));
+    // flag claims (bitmap levels mark vertices with byte stores): the init
+    // clears the flags of a search that uses them
+    uint8_t* const flags =
+        (g->claim_mode == 2 || (g->claim_mode == 1 && g->V <= kFlagAutoMaxV)) ? g->found : nullptr;
     BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, lv_s, pa_s, g->vis, g->vis_old,
-                            g->q[0], g->ctrl, grid_cap, g->rank ? 0 : 1));
+                            g->q[0], g->ctrl, grid_cap, g->rank ? 0 : 1, flags));
     const int32_t sum_words = g->summary_words;
     const int xgrid_full = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, 0));
     const int xgrid_sum = g->num_cus * std::min(g->grid_wgs, expand_blocks_per_cu(g->ept, sum_words));
@@ -628,7 +639,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
                                   g->tile_k, g->s_col, g->summary, lds_sum ? sum_words : 0,
                                   g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, lv_s,
-                                  pa_s, lvl, Qn, g->ctrl));
+                                  pa_s, lvl, Qn, g->ctrl, flags));
         xlaunches++;
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[2], s));
         const bool maybe_bitmap = (allow_bitmap == 2 && rmax > 0) || (allow_bitmap == 1 && rmax > T);
@@ -638,7 +649,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
             // the direction-optimizing mode also sums the next frontier's
             // degrees, so the next level's direction is known without a scan
             BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->vis, g->vis_old, Qn, lv_s,
-                                               lvl, g->ctrl, dir_opt ? g->s_off : nullptr));
+                                               lvl, g->ctrl, dir_opt ? g->s_off : nullptr, flags));
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
         BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -657,6 +668,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         examined += r;
         xbytes += 4 * r + 20 * (int64_t)qlen + (parents ? 4 : 0) * (int64_t)qn +
                   (bm ? 0 : 8 * (int64_t)qn);
+
         xalg += 4 * (r + (skip_rows ? g->h_ctrl->skipped : 0)) + (parents ? 8 : 4) * (int64_t)qn;
         if (qn == 0) break;
         if (bm) bitmap_levels++;

@@ -17,6 +17,10 @@ constexpr int kSkipLow = 16;          // row prefix skip thresholds 2^(16 + i) .
 constexpr int kSkipLevels = 10;       // ... for i = 0..9
 constexpr int kBigTiles = 16;         // scan: an entry spanning this many tiles or more ...
 constexpr int kBigTileList = 256;     // ... is queued (up to this many per block) for the workgroup
+// Flag claims (BFS_OPT_CLAIM_MODE 1) are used up to this many vertices: one
+// flag byte per vertex, probed at random, stays within the caches up to
+// there; beyond it the atomic claim of Algorithm 3 measured faster.
+constexpr int32_t kFlagAutoMaxV = 1 << 24;
 
 // Per-level control block in device memory.  The host reads it back once
 // per level; the kernels read the fields they need directly.
@@ -62,7 +66,7 @@ struct alignas(64) Ctrl {
 hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root,
                        const int32_t* rank, int32_t* level, int32_t* parent,
                        uint32_t* vis, uint32_t* vis_old, int32_t* Q, Ctrl* ctrl,
-                       int grid_cap, int fill);
+                       int grid_cap, int fill, uint8_t* found = nullptr);
 
 // Degree scan of the frontier Q: deg, cumul (exclusive, cumul[qlen] = r),
 // rowstart[k] = off[Q[k]], uidv[k] = uid_map ? uid_map[Q[k]] : Q[k], and
@@ -91,7 +95,8 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                          const int32_t* col,
                          const uint32_t* summary, int32_t summary_words, int32_t shift,
                          int use_prefix, uint32_t* vis, uint32_t* vis_old, int32_t* level,
-                         int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl);
+                         int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl,
+                         uint8_t* found = nullptr);
 
 // Single-root persistent loop for runs of small levels (smallloop.hip).
 // Zeroed by the host before each launch.
@@ -139,7 +144,8 @@ int expand_blocks_per_cu(int ept, int summary_words);
 // (from these row offsets) to ctrl->next_deg.
 hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
                                   uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
-                                  Ctrl* ctrl, const int64_t* deg_off = nullptr);
+                                  Ctrl* ctrl, const int64_t* deg_off = nullptr,
+                                  uint8_t* found = nullptr);
 
 // Degree order: caller-ordered outputs from the internal-id ones.
 hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank,

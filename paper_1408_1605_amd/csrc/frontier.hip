@@ -34,7 +34,8 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
                                               uint32_t* __restrict__ vis,
                                               uint32_t* __restrict__ vis_old,
                                               int32_t* __restrict__ Q, Ctrl* __restrict__ ctrl,
-                                              int vec, int fill)
+                                              int vec, int fill, uint4* __restrict__ found16,
+                                              int64_t n_found16)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
         level[v] = v == rin ? 0 : -1;
         if (parent) parent[v] = v == rin ? root : -1;
     }
+    for (int64_t i = tid; i < n_found16; i += stride) found16[i] = make_uint4(0u, 0u, 0u, 0u);
     const int64_t rw = rin >> 5;
     const uint32_t rb = 1u << (rin & 31);
     for (int64_t i = tid; i < W; i += stride) {
@@ -96,17 +98,21 @@ __global__ __launch_bounds__(kWG) void k_init(int32_t V, int32_t W, int32_t root
 
 hipError_t launch_init(hipStream_t s, int32_t V, int32_t W, int32_t root, const int32_t* rank,
                        int32_t* level, int32_t* parent, uint32_t* vis, uint32_t* vis_old,
-                       int32_t* Q, Ctrl* ctrl, int grid_cap, int fill)
+                       int32_t* Q, Ctrl* ctrl, int grid_cap, int fill, uint8_t* found)
 {
     const bool vec = ((uintptr_t)level % 16 == 0) &&
                      (parent == nullptr || (uintptr_t)parent % 16 == 0);
+    // the flags are padded to whole words: W * 32 bytes
+    const int64_t n_found16 = found ? (int64_t)W * 2 : 0;
     int64_t work = fill ? (int64_t)(vec ? V / 4 : V) : 0;
     if (W > work) work = W;
+    if (n_found16 > work) work = n_found16;
     int64_t grid = (work + kWG - 1) / kWG;
     if (grid > grid_cap) grid = grid_cap;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(kWG), 0, s, V, W, root, rank, level,
-                       parent, vis, vis_old, Q, ctrl, vec ? 1 : 0, fill);
+                       parent, vis, vis_old, Q, ctrl, vec ? 1 : 0, fill,
+                       reinterpret_cast<uint4*>(found), n_found16);
     return hipGetLastError();
 }
 
@@ -467,7 +473,8 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
                                                 int32_t* __restrict__ level,
                                                 int32_t* __restrict__ parent, int32_t lvl,
                                                 int32_t* __restrict__ Qn,
-                                                Ctrl* __restrict__ ctrl)
+                                                Ctrl* __restrict__ ctrl,
+                                                uint8_t* __restrict__ found)
 {
     __shared__ TileLds<EPT> L;
     extern __shared__ uint32_t s_sum[];
@@ -475,6 +482,9 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
     const int64_t r = ctrl->r;
     const int32_t ntiles = ctrl->ntiles;
     const bool list_out = ctrl->bitmap_out == 0;
+    // flag claims: a bitmap level marks its vertices with byte stores
+    // instead of claiming bits (below)
+    const bool flags = found != nullptr && !list_out;
     const int32_t skip_below = use_prefix ? ctrl->full_prefix : 0;
     if ((int32_t)blockIdx.x >= ntiles) return;  // whole workgroup: uniform
 
@@ -504,14 +514,36 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
         }
         // the next tile's staging loads overlap this tile's probes and claims
         cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
-        // claims: issue every atomic before using any result
         bool need[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) need[j] = !known[j] && !(wd[j] & (1u << (vv[j] & 31)));
+        if (flags) {
+            // A bitmap level needs no exactly-once claim: its next frontier is
+            // the set of flagged vertices, taken by k_bitmap_to_queue.  A
+            // vertex not visited before the level gets its flag byte set
+            // (byte stores never disturb neighbouring flags, so no atomic is
+            // needed) and a parent from the frontier; when several threads
+            // flag it in the same level, each stores a valid parent and one
+            // of them remains.  The flag is read first so that most repeat
+            // visits store nothing.
+            uint8_t fl[EPT];
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) fl[j] = need[j] ? found[vv[j]] : (uint8_t)1;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                if (!fl[j]) {
+                    found[vv[j]] = 1;
+                    if (parent) __builtin_nontemporal_store(uu[j], parent + vv[j]);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        // claims: issue every atomic before using any result
         uint32_t old[EPT];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            need[j] = !known[j] && !(wd[j] & (1u << (vv[j] & 31)));
+        for (int j = 0; j < EPT; ++j)
             if (need[j]) old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
-        }
         bool win[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) win[j] = need[j] && !(old[j] & (1u << (vv[j] & 31)));
@@ -559,7 +591,7 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                          const int32_t* col, const uint32_t* summary,
                          int32_t summary_words, int32_t shift, int use_prefix, uint32_t* vis,
                          uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
-                         int32_t* Qn, Ctrl* ctrl)
+                         int32_t* Qn, Ctrl* ctrl, uint8_t* found)
 {
     if (grid < 1) grid = 1;
     if (summary_words < 0 || summary == nullptr) summary_words = 0;
@@ -570,7 +602,7 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                            tile_k, col, summary, summary_words, shift, use_prefix, vis,           \
                            vis_old,                                                              \
                            level, parent,                                                        \
-                           lvl, Qn, ctrl);                                                       \
+                           lvl, Qn, ctrl, found);                                                \
         break;
     switch (ept) {
         BFS_EXPAND_CASE(1)
@@ -613,7 +645,8 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
                                                          int32_t* __restrict__ Qn,
                                                          int32_t* __restrict__ level,
                                                          int32_t lvl, Ctrl* __restrict__ ctrl,
-                                                         const int64_t* __restrict__ deg_off)
+                                                         const int64_t* __restrict__ deg_off,
+                                                         uint4* __restrict__ found16)
 {
     if (!ctrl->bitmap_out) return;
     __shared__ uint32_t s_f[kBitmapWordsPerWG];
@@ -626,7 +659,25 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
         const int64_t i = blk * kBitmapWordsPerWG + threadIdx.x;
         uint32_t f = 0;
         if (i < W) {
-            const uint32_t a = vis[i];
+            uint32_t a = vis[i];
+            if (found16) {
+                // the level's flag bytes (0 or 1) of this word's 32 ids
+                // become bits; the flags are cleared for the next level
+                const uint4 x = found16[2 * i], y = found16[2 * i + 1];
+                const uint32_t q[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+                uint32_t pf = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t z = q[k];
+                    pf |= ((z & 1u) | ((z >> 7) & 2u) | ((z >> 14) & 4u) | ((z >> 21) & 8u)) << (4 * k);
+                }
+                if (pf) {
+                    a |= pf;
+                    vis[i] = a;
+                    found16[2 * i] = make_uint4(0u, 0u, 0u, 0u);
+                    found16[2 * i + 1] = make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
             const uint32_t b = vis_old[i];
             f = a & ~b;
             if (f) vis_old[i] = a;
@@ -666,11 +717,11 @@ __global__ __launch_bounds__(kWG) void k_bitmap_to_queue(int32_t V, int32_t W,
 
 hipError_t launch_bitmap_to_queue(hipStream_t s, int grid, int32_t V, int32_t W, uint32_t* vis,
                                   uint32_t* vis_old, int32_t* Qn, int32_t* level, int32_t lvl,
-                                  Ctrl* ctrl, const int64_t* deg_off)
+                                  Ctrl* ctrl, const int64_t* deg_off, uint8_t* found)
 {
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid), dim3(kWG), 0, s, V, W, vis, vis_old, Qn,
-                       level, lvl, ctrl, deg_off);
+                       level, lvl, ctrl, deg_off, reinterpret_cast<uint4*>(found));
     return hipGetLastError();
 }
 

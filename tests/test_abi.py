@@ -189,3 +189,15 @@ def test_noalloc_size_limit(lib):
     assert so.bfs_run_noalloc(0, 0, 256, 256, 0, 256, None, None, None) == lib.BFS_ERR_INVALID
     assert so.bfs_run_noalloc(10, 5, None, 256, 0, 256, None, None, None) == lib.BFS_ERR_INVALID
     assert so.bfs_run_noalloc(10, 5, 256, 256, 10, 256, None, None, None) == lib.BFS_ERR_INVALID
+
+
+def test_binding_constants_match_header(lib):
+    # every BFS_* integer macro of the header has the same value in the
+    # binding (status codes, flags, option keys)
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = dict(re.findall(r"^\s*#define\s+(BFS_[A-Z0-9_]+)\s+(-?(?:0x)?[0-9a-fA-F]+)u?\s*$", text,
+                           flags=re.M))
+    assert "BFS_OPT_CLAIM_MODE" in defs and "BFS_ERR_TICKET" in defs
+    for name, val in defs.items():
+        assert hasattr(lib, name), name
+        assert getattr(lib, name) == int(val, 0), name

@@ -333,3 +333,92 @@ def test_device_loop_frontier_at_capacity(bfsmi, fans, dord):
     assert st.device_loop_levels == (st.levels if width <= 65536 else st.levels - 1)
     check(bfsmi, g, G, g.V - 1)
     G.close()
+
+
+# ---------------------------------------------------------------------------
+# Claim modes of the bitmap levels (BFS_OPT_CLAIM_MODE): the atomicOr claim
+# of Algorithm 3 (0), byte flags (2) and the size-based choice (1) give the
+# same levels and valid parents.
+
+@pytest.mark.parametrize("claim", [0, 1, 2])
+@pytest.mark.parametrize("scale", [12, 16, 18])
+def test_claim_modes_rmat(bfsmi, claim, scale):
+    g = graphgen.rmat(scale)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, claim)
+    assert G.get_option(bfsmi.BFS_OPT_CLAIM_MODE) == claim
+    if scale < 16:
+        # small graphs run every level in the persistent loop by default
+        G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)
+    roots = graphgen.pick_roots(g, 6, graphgen.root_seed(scale))
+    nbitmap = 0
+    for r in roots:
+        st = check(bfsmi, g, G, int(r))
+        nbitmap += st.bitmap_levels
+    assert nbitmap > 0  # the bitmap levels (where the modes differ) ran
+
+
+@pytest.mark.parametrize("claim", [0, 2])
+@pytest.mark.parametrize("fmode", [1, 2])
+def test_claim_modes_frontier_forms(bfsmi, claim, fmode):
+    # list-only levels never use flags; bitmap-whenever-possible levels
+    # flag every level the host drives
+    g = graphgen.rmat(14)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, claim)
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)  # every level from the host
+    for r in graphgen.pick_roots(g, 4, graphgen.root_seed(14)):
+        check(bfsmi, g, G, int(r), mode=fmode)
+
+
+def test_claim_flags_cleared_between_searches(bfsmi):
+    # flags set by one search must not leak into the next: alternate roots
+    # in different components and sizes on one handle, with and without
+    # parents
+    a = graphgen.rmat(13)
+    n = a.V
+    # two copies of the graph side by side: roots in either half
+    src = np.repeat(np.arange(2 * n), np.diff(np.concatenate([a.off, a.off[1:] + a.nnz])))
+    dst = np.concatenate([a.col, a.col + n])
+    g = graphgen.from_edges(2 * n, src, dst)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, 2)
+    roots = graphgen.pick_roots(g, 8, 77)
+    for i, r in enumerate(roots):
+        check(bfsmi, g, G, int(r), want_parents=(i % 2 == 0))
+
+
+@pytest.mark.parametrize("claim", [0, 2])
+def test_claim_modes_direction_optimizing(bfsmi, claim):
+    g = graphgen.rmat(16)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, claim)
+    G.set_option(bfsmi.BFS_OPT_DIRECTION, 1)
+    for r in graphgen.pick_roots(g, 4, graphgen.root_seed(16)):
+        check(bfsmi, g, G, int(r))
+
+
+@pytest.mark.parametrize("w,h", [(37, 23), (300, 200)])
+def test_claim_flags_grids(bfsmi, w, h):
+    g = graphgen.grid(w, h)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, 2)
+    G.set_option(bfsmi.BFS_OPT_FRONTIER_MODE, 2)
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)
+    for root in (0, w * h - 1, (h // 2) * w + w // 3):
+        lv, pa, st = G.run(root)
+        torch.cuda.synchronize()
+        r0, c0 = divmod(root, w)
+        rr, cc = np.divmod(np.arange(w * h), w)
+        assert np.array_equal(lv.cpu().numpy(), np.abs(rr - r0) + np.abs(cc - c0))
+        code, bad = oracle.validate(g.off, g.col, root, lv.cpu().numpy(), pa.cpu().numpy())
+        assert code == 0, (oracle.INVARIANTS[code], bad)
+
+
+def test_claim_mode_rejects_bad_values(bfsmi):
+    g = graphgen.rmat(10)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    for bad in (-1, 3):
+        with pytest.raises(bfsmi.BFSError):
+            G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, bad)
+    assert G.get_option(bfsmi.BFS_OPT_CLAIM_MODE) == 1
