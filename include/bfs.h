@@ -128,8 +128,10 @@ extern "C" {
                                       the frontier, and the flags become
                                       bitmap bits when the frontier is
                                       compacted; 1 (default): 2 when V is at
-                                      most 2^24 (flags of at most 16 MiB),
-                                      else 0.  Levels whose next frontier is
+                                      most 2^25, else 2 for the levels that
+                                      start with at least V/16 vertices
+                                      visited and 0 for the others.  Levels
+                                      whose next frontier is
                                       a list always claim with atomicOr.
                                       Every mode gives the same levels and
                                       valid parents                          */

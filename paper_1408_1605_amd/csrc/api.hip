@@ -503,9 +503,8 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
     int32_t* pa_s = parents ? (g->rank ? g->par_int : parents) : nullptr;
     if (timed) BFS_HIP_TRY(hipEventRecord(g->ev0, s));
     // flag claims (bitmap levels mark vertices with byte stores): the init
-    // clears the flags of a search that uses them
-    uint8_t* const flags =
-        (g->claim_mode == 2 || (g->claim_mode == 1 && g->V <= kFlagAutoMaxV)) ? g->found : nullptr;
+    // clears the flags of a search that may use them
+    uint8_t* const flags = g->claim_mode != 0 ? g->found : nullptr;
     BFS_HIP_TRY(launch_init(s, g->V, g->W, root, g->rank, lv_s, pa_s, g->vis, g->vis_old,
                             g->q[0], g->ctrl, grid_cap, g->rank ? 0 : 1, flags));
     const int32_t sum_words = g->summary_words;
@@ -636,10 +635,19 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
             }
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
+        // flags for this level's bitmap form: always in mode 2; in mode 1
+        // on graphs whose flags stay in the caches, and on larger graphs once
+        // a sixteenth of the vertices is visited (most probes then stop at
+        // the visited bit and few flags are read; measured per level on
+        // R-MAT 26: faster there, slower at the level after the hubs)
+        uint8_t* const lflags =
+            (g->claim_mode == 2 || (g->claim_mode == 1 && (g->V <= kFlagAutoMaxV ||
+                                                            reached * 16 >= (int64_t)g->V)))
+                ? flags : nullptr;
         BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
                                   g->tile_k, g->s_col, g->summary, lds_sum ? sum_words : 0,
                                   g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, lv_s,
-                                  pa_s, lvl, Qn, g->ctrl, flags));
+                                  pa_s, lvl, Qn, g->ctrl, lflags));
         xlaunches++;
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[2], s));
         const bool maybe_bitmap = (allow_bitmap == 2 && rmax > 0) || (allow_bitmap == 1 && rmax > T);
@@ -649,7 +657,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
             // the direction-optimizing mode also sums the next frontier's
             // degrees, so the next level's direction is known without a scan
             BFS_HIP_TRY(launch_bitmap_to_queue(s, grid2, g->V, g->W, g->vis, g->vis_old, Qn, lv_s,
-                                               lvl, g->ctrl, dir_opt ? g->s_off : nullptr, flags));
+                                               lvl, g->ctrl, dir_opt ? g->s_off : nullptr, lflags));
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
         BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));

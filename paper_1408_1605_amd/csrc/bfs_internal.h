@@ -17,10 +17,10 @@ constexpr int kSkipLow = 16;          // row prefix skip thresholds 2^(16 + i) .
 constexpr int kSkipLevels = 10;       // ... for i = 0..9
 constexpr int kBigTiles = 16;         // scan: an entry spanning this many tiles or more ...
 constexpr int kBigTileList = 256;     // ... is queued (up to this many per block) for the workgroup
-// Flag claims (BFS_OPT_CLAIM_MODE 1) are used up to this many vertices: one
-// flag byte per vertex, probed at random, stays within the caches up to
-// there; beyond it the atomic claim of Algorithm 3 measured faster.
-constexpr int32_t kFlagAutoMaxV = 1 << 24;
+// Flag claims (BFS_OPT_CLAIM_MODE 1) are used at every bitmap level up to
+// this many vertices (one flag byte per vertex, probed at random; measured
+// faster than the atomic claim of Algorithm 3 on R-MAT 16-25).
+constexpr int32_t kFlagAutoMaxV = 1 << 25;
 
 // Per-level control block in device memory.  The host reads it back once
 // per level; the kernels read the fields they need directly.
