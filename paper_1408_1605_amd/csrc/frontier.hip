@@ -745,13 +745,51 @@ __global__ __launch_bounds__(kWG) void k_finish(int32_t V, const int32_t* __rest
                                                 const int32_t* __restrict__ lvl_int,
                                                 const int32_t* __restrict__ par_int,
                                                 int32_t* __restrict__ level,
-                                                int32_t* __restrict__ parent)
+                                                int32_t* __restrict__ parent, int vec)
 {
+    constexpr int kPer = kFinishChunk / kWG;  // ids per thread and chunk
     const int64_t nchunks = ((int64_t)V + kFinishChunk - 1) / kFinishChunk;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int64_t c0 = ch * kFinishChunk;
+        if (vec && c0 + kFinishChunk <= V) {
+            // a whole chunk: thread t owns ids c0 + 4 t + 1024 j + (0..3);
+            // every load of the chunk is issued before the first is used
+            int4 x[kPer / 4];
+#pragma unroll
+            for (int j = 0; j < kPer / 4; ++j)
+                x[j] = *reinterpret_cast<const int4*>(rank + c0 + j * 4 * kWG + 4 * threadIdx.x);
+            uint32_t w[kPer];
+#pragma unroll
+            for (int j = 0; j < kPer / 4; ++j) {
+                w[4 * j + 0] = vis[x[j].x >> 5];
+                w[4 * j + 1] = vis[x[j].y >> 5];
+                w[4 * j + 2] = vis[x[j].z >> 5];
+                w[4 * j + 3] = vis[x[j].w >> 5];
+            }
+            int32_t l[kPer], p[kPer];
+#pragma unroll
+            for (int j = 0; j < kPer / 4; ++j) {
+                const int32_t xs[4] = {x[j].x, x[j].y, x[j].z, x[j].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bool on = (w[4 * j + k] >> (xs[k] & 31)) & 1u;
+                    l[4 * j + k] = on ? lvl_int[xs[k]] : -1;
+                    p[4 * j + k] = (on && parent) ? par_int[xs[k]] : -1;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kPer / 4; ++j) {
+                const int64_t c = c0 + j * 4 * kWG + 4 * threadIdx.x;
+                *reinterpret_cast<int4*>(level + c) =
+                    make_int4(l[4 * j], l[4 * j + 1], l[4 * j + 2], l[4 * j + 3]);
+                if (parent)
+                    *reinterpret_cast<int4*>(parent + c) =
+                        make_int4(p[4 * j], p[4 * j + 1], p[4 * j + 2], p[4 * j + 3]);
+            }
+            continue;
+        }
 #pragma unroll 4
-        for (int j = 0; j < kFinishChunk / kWG; ++j) {
+        for (int j = 0; j < kPer; ++j) {
             const int64_t c = c0 + j * kWG + threadIdx.x;
             if (c < V) {
                 const int32_t x = rank[c];
@@ -774,8 +812,11 @@ hipError_t launch_finish(hipStream_t s, int grid, int32_t V, const int32_t* rank
     const int64_t nchunks = ((int64_t)V + kFinishChunk - 1) / kFinishChunk;
     if (grid > nchunks) grid = (int)nchunks;
     if (grid < 1) grid = 1;
+    // 16-byte rank loads and output stores when the caller's arrays allow
+    const bool vec = (uintptr_t)rank % 16 == 0 && (uintptr_t)level % 16 == 0 &&
+                     (parent == nullptr || (uintptr_t)parent % 16 == 0);
     hipLaunchKernelGGL(k_finish, dim3(grid), dim3(kWG), 0, s, V, rank, vis, lvl_int, par_int,
-                       level, parent);
+                       level, parent, vec ? 1 : 0);
     return hipGetLastError();
 }
 
