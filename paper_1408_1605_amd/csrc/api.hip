@@ -660,6 +660,20 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
                                                lvl, g->ctrl, dir_opt ? g->s_off : nullptr, lflags));
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[3], s));
+        // the persistent loop is queued right behind the level, before the
+        // read-back: it takes the next frontier from the control block and
+        // runs nothing when that is empty or too large, so a run of small
+        // levels after a heavy one costs no extra host round trip
+        const bool spec = dev_ok && !dir_opt;
+        if (spec) {
+            BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
+            BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
+            BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
+                                            g->vis, g->vis_old, Qn, g->q[cur], lv_s, pa_s,
+                                            g->small_sync, g->small_side, g->ctrl, -1, lvl + 1,
+                                            g->small_limit, (int64_t)g->small_grid * kSmallDeg,
+                                            kSmallDeg));
+        }
         BFS_HIP_TRY(hipMemcpyAsync(g->h_ctrl, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
         BFS_HIP_TRY(hipStreamSynchronize(s));
         if (g->h_ctrl->err)
@@ -685,6 +699,23 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         qlen = (int32_t)qn;
         cur ^= 1;
         lvl++;
+        if (spec) {
+            // what the queued persistent loop did with the next frontier
+            const Ctrl& c = *g->h_ctrl;
+            dev_left = true;  // a frontier it handed back goes to the host path
+            if (c.steps > 0) {
+                reached += c.reached;
+                nlevels += c.levels;
+                edges += c.r_total;
+                examined += c.r_total;
+                dev_levels += c.steps;
+                cur = (cur + c.steps) & 1;
+                lvl = c.level;
+                qlen = c.qlen;
+                if (c.done == 1) break;  // the frontier ran empty
+            }
+            continue;
+        }
         if (dir_opt && bm && !bu_done) {
             // the compaction summed the new frontier's degrees: decide its
             // level's direction now (Beamer et al.'s test)

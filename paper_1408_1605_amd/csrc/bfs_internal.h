@@ -123,6 +123,9 @@ struct SmallSide {
     int32_t cap;
 };
 int small_loop_blocks();
+// qlen < 0: the frontier size is read from ctrl->qn_count (the previous
+// host-driven level's output); the loop then runs no level when it is 0 or
+// above qlimit.
 hipError_t launch_small_levels(hipStream_t s, int grid, int32_t V, const int64_t* off,
                                const int32_t* col, const int32_t* orig, uint32_t* vis,
                                uint32_t* vis_old, int32_t* Qa, int32_t* Qb, int32_t* level,

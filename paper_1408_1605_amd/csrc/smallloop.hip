@@ -86,6 +86,23 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
     const int t = threadIdx.x;
     const int wave = t >> 6;
     if (t == 0) s_epoch = 0;
+    // qlen0 < 0: launched right behind a host-driven level, whose next
+    // frontier size is in ctrl->qn_count; an empty frontier ends the search
+    // and one above the limits goes back to the host, both before any level
+    if (qlen0 < 0) {
+        qlen0 = (int32_t)ctrl->qn_count;
+        if (qlen0 == 0 || qlen0 > qlimit || qlen0 > side.cap) {
+            if (w == 0 && t == 0) {
+                ctrl->done = qlen0 == 0 ? 1 : 2;
+                ctrl->qlen = qlen0;
+                ctrl->level = lvl0;
+                ctrl->steps = 0;
+                ctrl->reached = 0;
+                ctrl->levels = 0;
+            }
+            return;
+        }
+    }
 
     // The first frontier's size limits are checked before any level runs.
     {
