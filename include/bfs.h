@@ -135,6 +135,20 @@ extern "C" {
                                       a list always claim with atomicOr.
                                       Every mode gives the same levels and
                                       valid parents                          */
+#define BFS_OPT_XCD_SLICES      15 /* degree-ordered graphs: 1 (default) runs the
+                                      early host-driven levels of graphs with
+                                      at least 2^23 vertices (frontier and
+                                      visited set both at most V/64) as XCD-
+                                      sliced levels: the ids are dealt to 8
+                                      slices by 1024-id blocks (one line of
+                                      the visited bitmap each), every row is
+                                      also stored grouped by slice, and
+                                      workgroup b of the expansion takes only
+                                      edges into slice b mod 8, so the XCD it
+                                      runs on probes one eighth of the
+                                      bitmap.  0 off; 2 every host-driven
+                                      level whose frontier has at most V/8
+                                      vertices.  Same levels, valid parents  */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;

@@ -43,6 +43,7 @@ BFS_OPT_DO_ALPHA = 10
 BFS_OPT_DO_BETA = 11
 BFS_OPT_LOOP_LIMIT = 12
 BFS_OPT_CLAIM_MODE = 13
+BFS_OPT_XCD_SLICES = 15
 
 BFS_SRV_NO_PERSISTENT = 0x1
 

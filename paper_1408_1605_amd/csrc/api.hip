@@ -93,6 +93,8 @@ WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags)
         L.par_int = take((size_t)V * 4);
         if (flags & BFS_WS_BATCH) L.ms_out = take((size_t)64 * V);  // batch rows by internal id
         L.found = take(W * 32);  // flag claims: one byte per id, padded to whole words
+        L.xo = take((size_t)V * kXcdSlices * 4);  // XCD slices: group offsets per row
+        // (the slice-grouped rows reuse col_tmp, free once creation is done)
     }
     L.total = p;
     return L;
@@ -154,6 +156,8 @@ void bind_workspace(bfs_graph* g, char* ws, const WsLayout& L, uint32_t flags)
         g->par_int = reinterpret_cast<int32_t*>(ws + L.par_int);
         if (flags & BFS_WS_BATCH) g->ms_out = reinterpret_cast<int8_t*>(ws + L.ms_out);
         g->found = reinterpret_cast<uint8_t*>(ws + L.found);
+        g->xo = reinterpret_cast<uint32_t*>(ws + L.xo);
+        g->col_x = reinterpret_cast<int32_t*>(ws + L.col_tmp);
     }
     if (flags & BFS_WS_BATCH) {
         g->ms_sn = reinterpret_cast<SeenNext*>(ws + L.ms_sn);
@@ -313,6 +317,9 @@ int bfs_graph_create(bfs_graph** out, int32_t V, int64_t nnz, const int64_t* d_r
         if (e == hipSuccess)
             e = build_row_skip(s, V, g->s_off, col_tmp, const_cast<int32_t*>(g->s_col), g->skip,
                                g->num_cus * 8);
+        // the rows grouped by XCD slice, in col_tmp's space (free from here on)
+        if (e == hipSuccess)
+            e = build_slice_rows(s, V, g->s_off, g->s_col, g->col_x, g->xo, g->num_cus * 8);
         // internal ids run in non-increasing degree class, so the vertices
         // with a neighbour are exactly the ids below their count
         uint32_t* d_cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->scratch) + 128);
@@ -409,6 +416,10 @@ int bfs_set_option(bfs_graph* g, int key, int64_t value)
         if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "claim mode must be 0..2");
         g->claim_mode = (int)value;
         break;
+    case BFS_OPT_XCD_SLICES:
+        if (value < 0 || value > 2) return fail(BFS_ERR_INVALID, "XCD slices must be 0..2");
+        g->xcd_slices = (int)value;
+        break;
     default:
         return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
@@ -432,6 +443,7 @@ int bfs_get_option(bfs_graph* g, int key, int64_t* value)
     case BFS_OPT_DO_ALPHA: *value = g->do_alpha; break;
     case BFS_OPT_DO_BETA: *value = g->do_beta; break;
     case BFS_OPT_CLAIM_MODE: *value = g->claim_mode; break;
+    case BFS_OPT_XCD_SLICES: *value = g->xcd_slices; break;
     default: return fail(BFS_ERR_INVALID, "unknown option %d", key);
     }
     return ok();
@@ -600,18 +612,34 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         // runs before the degree scan so the scan can drop row prefixes
         const bool use_sum = g->use_summary > 0 && rmax > T;
         const bool lds_sum = use_sum && g->use_summary == 2;
-        const bool skip_rows = use_sum && g->skip && g->row_skip;
-        const int grid = (int)std::max<int64_t>(
-            1, std::min<int64_t>(tiles_ub, lds_sum ? xgrid_sum : xgrid_full));
+        // XCD-sliced level: each XCD probes its eighth of the bitmap (for
+        // early levels with few, high-degree frontier vertices: the level
+        // after the hubs on large graphs); the row prefix skip is not used
+        const bool sliced =
+            g->xo && g->xcd_slices != 0 && !dir_opt && (int64_t)qlen * kXcdSlices <= g->V &&
+            (g->xcd_slices == 2 ||
+             (g->V >= kSliceMinV && reached * kXcdSlices <= (int64_t)g->V));
+        const bool skip_rows = use_sum && g->skip && g->row_skip && !sliced;
+        const int grid_cap_x = lds_sum ? xgrid_sum : xgrid_full;
+        const int grid = sliced
+            ? (int)std::max<int64_t>(kXcdSlices, std::min<int64_t>(
+                  (tiles_ub + 2 * kXcdSlices) / kXcdSlices * kXcdSlices, grid_cap_x))
+            : (int)std::max<int64_t>(1, std::min<int64_t>(tiles_ub, grid_cap_x));
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[0], s));
         if (use_sum) {
             const int gs = std::max(1, std::min(grid_cap, (g->summary_blocks + 31) / 32));
             BFS_HIP_TRY(launch_visited_summary(s, gs, g->V, g->W, g->vis, g->summary_shift,
                                                g->summary_blocks, g->summary, g->ctrl));
         }
-        BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
-                                g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
-                                g->ctrl, skip_rows ? g->skip : nullptr, g->V));
+        if (sliced)
+            BFS_HIP_TRY(launch_slice_scan(s, std::max(1, std::min(grid_cap, (qlen + kWG - 1) / kWG)),
+                                          Q, qlen, g->s_off, g->xo, g->orig, g->deg, g->rowstart,
+                                          g->suid, g->bsum, g->cumul, g->tile_k, tile_cap, tile, T,
+                                          allow_bitmap, g->ctrl));
+        else
+            BFS_HIP_TRY(launch_scan(s, Q, qlen, g->s_off, g->orig, g->deg, g->rowstart, g->suid,
+                                    g->bsum, g->cumul, g->tile_k, tile_cap, tile, T, allow_bitmap,
+                                    g->ctrl, skip_rows ? g->skip : nullptr, g->V));
         if (dir_opt && !bu_done) {
             // the frontier's edge count decides the direction (Beamer et
             // al.): bottom-up when it exceeds the unvisited vertices' edges
@@ -636,18 +664,22 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         }
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[1], s));
         // flags for this level's bitmap form: always in mode 2; in mode 1
-        // on graphs whose flags stay in the caches, and on larger graphs once
-        // a sixteenth of the vertices is visited (most probes then stop at
-        // the visited bit and few flags are read; measured per level on
-        // R-MAT 26: faster there, slower at the level after the hubs)
+        // on graphs whose flags stay in the caches, at XCD-sliced levels
+        // (each XCD then reads its eighth of the flags), and on larger
+        // graphs once a sixteenth of the vertices is visited (most probes
+        // then stop at the visited bit and few flags are read; measured per
+        // level on R-MAT 26: faster there, slower than the atomics at an
+        // unsliced level after the hubs)
         uint8_t* const lflags =
-            (g->claim_mode == 2 || (g->claim_mode == 1 && (g->V <= kFlagAutoMaxV ||
-                                                            reached * 16 >= (int64_t)g->V)))
+            (g->claim_mode == 2 ||
+             (g->claim_mode == 1 && (g->V <= kFlagAutoMaxV || sliced ||
+                                     reached * 16 >= (int64_t)g->V)))
                 ? flags : nullptr;
         BFS_HIP_TRY(launch_expand(s, g->ept, grid, g->V, g->rowstart, g->suid, g->cumul,
-                                  g->tile_k, g->s_col, g->summary, lds_sum ? sum_words : 0,
-                                  g->summary_shift, use_sum ? 1 : 0, g->vis, g->vis_old, lv_s,
-                                  pa_s, lvl, Qn, g->ctrl, lflags));
+                                  g->tile_k, sliced ? g->col_x : g->s_col, g->summary,
+                                  lds_sum ? sum_words : 0, g->summary_shift, use_sum ? 1 : 0,
+                                  g->vis, g->vis_old, lv_s, pa_s, lvl, Qn, g->ctrl, lflags,
+                                  sliced ? qlen : 0));
         xlaunches++;
         if (prof) BFS_HIP_TRY(hipEventRecord(g->pev[2], s));
         const bool maybe_bitmap = (allow_bitmap == 2 && rmax > 0) || (allow_bitmap == 1 && rmax > T);
@@ -688,7 +720,7 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         const bool bm = g->h_ctrl->bitmap_out != 0;
         edges += r + (skip_rows ? g->h_ctrl->skipped : 0);
         examined += r;
-        xbytes += 4 * r + 20 * (int64_t)qlen + (parents ? 4 : 0) * (int64_t)qn +
+        xbytes += 4 * r + 20 * (sliced ? kXcdSlices : 1) * (int64_t)qlen + (parents ? 4 : 0) * (int64_t)qn +
                   (bm ? 0 : 8 * (int64_t)qn);
 
         xalg += 4 * (r + (skip_rows ? g->h_ctrl->skipped : 0)) + (parents ? 8 : 4) * (int64_t)qn;

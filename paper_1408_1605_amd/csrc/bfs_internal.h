@@ -17,6 +17,15 @@ constexpr int kSkipLow = 16;          // row prefix skip thresholds 2^(16 + i) .
 constexpr int kSkipLevels = 10;       // ... for i = 0..9
 constexpr int kBigTiles = 16;         // scan: an entry spanning this many tiles or more ...
 constexpr int kBigTileList = 256;     // ... is queued (up to this many per block) for the workgroup
+// XCD slices of the id space: the visited bitmap's 128-byte lines (1024 ids
+// each) dealt round-robin to eight slices; workgroup b of a launch runs on
+// XCD b mod 8, so an expansion whose workgroups b only probe slice b mod 8
+// keeps each XCD's probes within one eighth of the bitmap (its own L2).
+constexpr int kXcdSlices = 8;
+constexpr int32_t kSliceMinV = 1 << 17;  // automatic sliced levels from this many vertices
+constexpr int32_t kSliceHot = 1 << 13;   // ids below: dealt to slices by row, not by id
+__host__ __device__ __forceinline__ int xcd_slice(int32_t v) { return (v >> 10) & (kXcdSlices - 1); }
+
 // Flag claims (BFS_OPT_CLAIM_MODE 1) are used at every bitmap level up to
 // this many vertices (one flag byte per vertex, probed at random; measured
 // faster than the atomic claim of Algorithm 3 on R-MAT 16-25).
@@ -96,7 +105,16 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                          const uint32_t* summary, int32_t summary_words, int32_t shift,
                          int use_prefix, uint32_t* vis, uint32_t* vis_old, int32_t* level,
                          int32_t* parent, int32_t lvl, int32_t* Qn, Ctrl* ctrl,
-                         uint8_t* found = nullptr);
+                         uint8_t* found = nullptr, int32_t slice_q = 0);
+// XCD-sliced level: the scan of launch_scan over 8 * qlen entries, entry
+// s * qlen + k being slice s's group of frontier entry k's row in the
+// slice-grouped rows (offsets xo); then launch_expand with slice_q = qlen on
+// those rows.  Needs 8 * qlen <= V.
+hipError_t launch_slice_scan(hipStream_t s, int grid, const int32_t* Q, int32_t qlen,
+                             const int64_t* off, const uint32_t* xo, const int32_t* uid_map,
+                             int32_t* deg, int64_t* rowstart, int32_t* uidv, int64_t* bsum,
+                             int64_t* cumul, int32_t* tile_k, int64_t tile_cap, int tile,
+                             int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl);
 
 // Single-root persistent loop for runs of small levels (smallloop.hip).
 // Zeroed by the host before each launch.
@@ -269,5 +287,9 @@ hipError_t launch_validate_csr(hipStream_t s, int32_t V, int64_t nnz,
 // below 2^(16 + i), i < kSkipLevels.
 hipError_t build_row_skip(hipStream_t s, int32_t V, const int64_t* off, const int32_t* col_in,
                           int32_t* col_out, int32_t* skip, int grid);
+// XCD slices (rowskip.hip): col_out = each row of col_in grouped by
+// xcd_slice (stable), xo[x * 8 + s] = offset of slice s's group in row x.
+hipError_t build_slice_rows(hipStream_t s, int32_t V, const int64_t* off, const int32_t* col_in,
+                            int32_t* col_out, uint32_t* xo, int grid);
 
 }  // namespace bfsmi

@@ -156,7 +156,9 @@ __global__ __launch_bounds__(kWG) void k_scan_reduce(const int32_t* __restrict__
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
             const int64_t k = base + j * kWG + threadIdx.x;
-            if (k < qlen) {
+            if (k < qlen && !Q) {
+                sum += deg[k];  // entries prefilled (k_slice_entries)
+            } else if (k < qlen) {
                 const int32_t u = Q[k];
                 int64_t a = off[u];
                 int64_t d = off[u + 1] - a;
@@ -305,6 +307,51 @@ __global__ __launch_bounds__(kWG) void k_scan_down(const int32_t* __restrict__ d
         }
         __syncthreads();  // s_deg and s_cum are reused by the next block
     }
+}
+
+// XCD-sliced level: frontier entry k becomes the eight entries s * qlen + k
+// (s = 0..7), the slice-s group of its row (grouped rows col_x, offsets xo;
+// row starts as in off), so one scan over 8 * qlen entries numbers the
+// edges slice by slice.
+__global__ __launch_bounds__(kWG) void k_slice_entries(const int32_t* __restrict__ Q, int32_t qlen,
+                                                       const int64_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ xo,
+                                                       const int32_t* __restrict__ uid_map,
+                                                       int32_t* __restrict__ deg,
+                                                       int64_t* __restrict__ rowstart,
+                                                       int32_t* __restrict__ uidv)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < qlen;
+         k += (int64_t)gridDim.x * kWG) {
+        const int32_t u = Q[k];
+        const int64_t a = off[u];
+        const uint32_t d = (uint32_t)(off[u + 1] - a);
+        const uint4 lo = *reinterpret_cast<const uint4*>(xo + (int64_t)u * kXcdSlices);
+        const uint4 hi = *reinterpret_cast<const uint4*>(xo + (int64_t)u * kXcdSlices + 4);
+        const uint32_t st[kXcdSlices + 1] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w, d};
+        const int32_t id = uid_map ? uid_map[u] : u;
+#pragma unroll
+        for (int s = 0; s < kXcdSlices; ++s) {
+            const int64_t i = (int64_t)s * qlen + k;
+            deg[i] = (int32_t)(st[s + 1] - st[s]);
+            rowstart[i] = a + st[s];
+            uidv[i] = id;
+        }
+    }
+}
+
+hipError_t launch_slice_scan(hipStream_t s, int grid, const int32_t* Q, int32_t qlen,
+                             const int64_t* off, const uint32_t* xo, const int32_t* uid_map,
+                             int32_t* deg, int64_t* rowstart, int32_t* uidv, int64_t* bsum,
+                             int64_t* cumul, int32_t* tile_k, int64_t tile_cap, int tile,
+                             int64_t bitmap_threshold, int allow_bitmap, Ctrl* ctrl)
+{
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_slice_entries, dim3(grid), dim3(kWG), 0, s, Q, qlen, off, xo, uid_map, deg,
+                       rowstart, uidv);
+    // the scan proper over the 8 * qlen prefilled entries (Q == nullptr)
+    return launch_scan(s, nullptr, kXcdSlices * qlen, off, nullptr, deg, rowstart, uidv, bsum,
+                       cumul, tile_k, tile_cap, tile, bitmap_threshold, allow_bitmap, ctrl);
 }
 
 hipError_t launch_scan(hipStream_t s, const int32_t* Q, int32_t qlen, const int64_t* off,
@@ -474,7 +521,7 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
                                                 int32_t* __restrict__ parent, int32_t lvl,
                                                 int32_t* __restrict__ Qn,
                                                 Ctrl* __restrict__ ctrl,
-                                                uint8_t* __restrict__ found)
+                                                uint8_t* __restrict__ found, int32_t slice_q)
 {
     __shared__ TileLds<EPT> L;
     extern __shared__ uint32_t s_sum[];
@@ -486,17 +533,38 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
     // instead of claiming bits (below)
     const bool flags = found != nullptr && !list_out;
     const int32_t skip_below = use_prefix ? ctrl->full_prefix : 0;
-    if ((int32_t)blockIdx.x >= ntiles) return;  // whole workgroup: uniform
+    // XCD-sliced level (slice_q > 0: the scan numbered the edges slice by
+    // slice, slice s owning edges [cumul[s * slice_q], cumul[(s + 1) *
+    // slice_q])): workgroup b takes slice b mod 8 only, so the XCD it runs
+    // on probes one eighth of the bitmap; tiles on a slice boundary are
+    // shared by both slices, each taking its own edges
+    int32_t t_first = blockIdx.x, t_end = ntiles, t_step = gridDim.x;
+    int64_t e_lo = 0, e_hi = r;
+    if (slice_q > 0) {
+        constexpr int64_t TILE = TileLds<EPT>::TILE;
+        const int sl = blockIdx.x & (kXcdSlices - 1);
+        e_lo = cumul[(int64_t)sl * slice_q];
+        e_hi = cumul[(int64_t)(sl + 1) * slice_q];
+        t_step = gridDim.x / kXcdSlices;
+        t_first = (int32_t)(e_lo / TILE) + (int32_t)(blockIdx.x / kXcdSlices);
+        t_end = (int32_t)((e_hi + TILE - 1) / TILE);
+        if (t_end > ntiles) t_end = ntiles;
+    }
+    if (t_first >= t_end) return;  // whole workgroup: uniform
 
-    StageRegs<EPT> cur = fetch_stage<EPT>(blockIdx.x, ntiles, cumul, rowstart, uidv, tile_k);
+    StageRegs<EPT> cur = fetch_stage<EPT>(t_first, t_end, cumul, rowstart, uidv, tile_k);
     for (int32_t w = threadIdx.x; w < summary_words; w += kWG) s_sum[w] = summary[w];
     __syncthreads();
 
-    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int32_t tile = t_first; tile < t_end; tile += t_step) {
         int32_t uu[EPT], vv[EPT];
         bool ok[EPT];
         int64_t ee[EPT];
         map_tile<EPT>(L, cur, r, cumul, rowstart, uidv, col, uu, vv, ok, ee);
+        if (slice_q > 0) {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) ok[j] = ok[j] && ee[j] >= e_lo && ee[j] < e_hi;
+        }
 
         // Early visited test: summary (register / LDS), else a plain load of
         // the bitmap word (a stale word only lets more threads try the atomic).
@@ -513,7 +581,7 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
             if (!known[j]) wd[j] = vis[v >> 5];
         }
         // the next tile's staging loads overlap this tile's probes and claims
-        cur = fetch_stage<EPT>(tile + gridDim.x, ntiles, cumul, rowstart, uidv, tile_k);
+        cur = fetch_stage<EPT>(tile + t_step, t_end, cumul, rowstart, uidv, tile_k);
         bool need[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) need[j] = !known[j] && !(wd[j] & (1u << (vv[j] & 31)));
@@ -591,9 +659,10 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                          const int32_t* col, const uint32_t* summary,
                          int32_t summary_words, int32_t shift, int use_prefix, uint32_t* vis,
                          uint32_t* vis_old, int32_t* level, int32_t* parent, int32_t lvl,
-                         int32_t* Qn, Ctrl* ctrl, uint8_t* found)
+                         int32_t* Qn, Ctrl* ctrl, uint8_t* found, int32_t slice_q)
 {
-    if (grid < 1) grid = 1;
+    if (slice_q > 0) grid = grid / kXcdSlices * kXcdSlices;  // every slice the same workgroups
+    if (grid < 1) grid = slice_q > 0 ? kXcdSlices : 1;
     if (summary_words < 0 || summary == nullptr) summary_words = 0;
     const size_t dyn = (size_t)summary_words * 4;
 #define BFS_EXPAND_CASE(E)                                                                        \
@@ -602,7 +671,7 @@ hipError_t launch_expand(hipStream_t s, int ept, int grid, int32_t V, const int6
                            tile_k, col, summary, summary_words, shift, use_prefix, vis,           \
                            vis_old,                                                              \
                            level, parent,                                                        \
-                           lvl, Qn, ctrl, found);                                                \
+                           lvl, Qn, ctrl, found, slice_q);                                       \
         break;
     switch (ept) {
         BFS_EXPAND_CASE(1)

@@ -78,6 +78,74 @@ __global__ __launch_bounds__(kWG) void k_row_partition(int32_t V, const int64_t*
     }
 }
 
+// XCD slices: slice(y) = (y >> 10) & 7 (one 128-byte line of the visited
+// bitmap per 1024 ids, the lines dealt round-robin to the eight slices),
+// except for the ids below kSliceHot, the hubs most edges point at: their
+// few bitmap lines stay in every L2, and they join slice x mod 8 of row x
+// so that no slice gets all of the densest lines' edges.
+// One wave per row: the row's ids grouped by slice (stable), xo[x * 8 + s]
+// = the offset of slice s's group within the row.
+__device__ __forceinline__ int row_slice(int32_t y, int64_t x)
+{
+    return y < kSliceHot ? (int)(x & (kXcdSlices - 1)) : xcd_slice(y);
+}
+
+__global__ __launch_bounds__(kWG) void k_slice_partition(int32_t V, const int64_t* __restrict__ off,
+                                                         const int32_t* __restrict__ col_in,
+                                                         int32_t* __restrict__ col_out,
+                                                         uint32_t* __restrict__ xo)
+{
+    const int lane = __lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (kWG / 64);
+    for (int64_t x = (int64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6); x < V; x += nwaves) {
+        const int64_t a = off[x], b = off[x + 1];
+        int64_t cnt[kXcdSlices];
+#pragma unroll
+        for (int k = 0; k < kXcdSlices; ++k) cnt[k] = 0;
+        for (int64_t e0 = a; e0 < b; e0 += 64) {
+            const int64_t e = e0 + lane;
+            const int sl = e < b ? row_slice(col_in[e], x) : -1;
+#pragma unroll
+            for (int k = 0; k < kXcdSlices; ++k) cnt[k] += __popcll(__ballot(sl == k));
+        }
+        int64_t cur[kXcdSlices];
+        int64_t run = a;
+#pragma unroll
+        for (int k = 0; k < kXcdSlices; ++k) {
+            cur[k] = run;
+            run += cnt[k];
+        }
+        if (lane < kXcdSlices) {
+            int64_t st = 0;
+#pragma unroll
+            for (int k = 0; k < kXcdSlices; ++k) st += k < lane ? cnt[k] : 0;
+            xo[x * kXcdSlices + lane] = (uint32_t)st;
+        }
+        for (int64_t e0 = a; e0 < b; e0 += 64) {
+            const int64_t e = e0 + lane;
+            const int32_t y = e < b ? col_in[e] : 0;
+            const int sl = e < b ? row_slice(y, x) : -1;
+#pragma unroll
+            for (int k = 0; k < kXcdSlices; ++k) {
+                const uint64_t m = __ballot(sl == k);
+                if (sl == k) col_out[cur[k] + lanes_below(m)] = y;
+                cur[k] += __popcll(m);
+            }
+        }
+    }
+}
+
+hipError_t build_slice_rows(hipStream_t s, int32_t V, const int64_t* off, const int32_t* col_in,
+                            int32_t* col_out, uint32_t* xo, int grid)
+{
+    int64_t g = ((int64_t)V + kWG / 64 - 1) / (kWG / 64);
+    if (g > grid) g = grid;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_slice_partition, dim3((unsigned)g), dim3(kWG), 0, s, V, off, col_in,
+                       col_out, xo);
+    return hipGetLastError();
+}
+
 hipError_t build_row_skip(hipStream_t s, int32_t V, const int64_t* off, const int32_t* col_in,
                           int32_t* col_out, int32_t* skip, int grid)
 {

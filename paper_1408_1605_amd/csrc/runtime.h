@@ -25,7 +25,7 @@ struct WsLayout {
     size_t vis, vis_old, q0, q1, deg, rowstart, suid, cumul, bsum, tile_k, ctrl, scratch, sync, sside, summary;
     size_t ms_sn, ms_front, ms_ctrl, ms_roots, ms_touched;
     size_t rank, orig, off_r, col_r, hist, col_tmp, skip, lvl_int, par_int, ms_out;
-    size_t found;
+    size_t found, xo;
     size_t total;
 };
 WsLayout ws_layout(int32_t V, int64_t nnz, uint32_t flags);
@@ -75,6 +75,8 @@ struct bfs_graph {
     int32_t* par_int = nullptr;  // parent (caller id) by internal id (degree order only)
     int8_t* ms_out = nullptr;    // batch: int8 rows by internal id (degree order + batch)
     uint8_t* found = nullptr;    // flag claims: one byte per id (degree order only)
+    uint32_t* xo = nullptr;      // XCD slices: per row, the offset of each slice's group
+    int32_t* col_x = nullptr;    // XCD slices: rows grouped by slice (degree order only)
 
     bfsmi::Ctrl* h_ctrl = nullptr;      // pinned host mirror
     bfsmi::Ctrl* h_ms_ctrl = nullptr;   // pinned host mirror
@@ -104,6 +106,7 @@ struct bfs_graph {
     int do_beta = 24;       // bottom-up -> top-down when frontier * beta < V and shrinking
     int symmetric = 0;      // the CSR equals its transpose (checked at creation)
     int32_t v_active = 0;   // degree order: internal ids below it have a neighbour (else V)
+    int xcd_slices = 1;     // 0 off, 1 auto, 2 whenever the frontier fits (8 * qlen <= V)
     int claim_mode = 1;     // bitmap levels: 0 atomic claims, 1 flag claims up to
                             // kFlagAutoMaxV vertices, 2 flag claims
     std::atomic<int> busy{0};

@@ -422,3 +422,73 @@ def test_claim_mode_rejects_bad_values(bfsmi):
         with pytest.raises(bfsmi.BFSError):
             G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, bad)
     assert G.get_option(bfsmi.BFS_OPT_CLAIM_MODE) == 1
+
+
+# ---------------------------------------------------------------------------
+# XCD-sliced levels (BFS_OPT_XCD_SLICES): rows grouped by the slice of their
+# targets, workgroup b of the expansion taking slice b mod 8 only.
+
+@pytest.mark.parametrize("xs", [0, 1, 2])
+@pytest.mark.parametrize("claim", [0, 1, 2])
+@pytest.mark.parametrize("scale", [13, 17])
+def test_xcd_slices_rmat(bfsmi, xs, claim, scale):
+    g = graphgen.rmat(scale)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_XCD_SLICES, xs)
+    G.set_option(bfsmi.BFS_OPT_CLAIM_MODE, claim)
+    assert G.get_option(bfsmi.BFS_OPT_XCD_SLICES) == xs
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)  # every level through the host path
+    for r in graphgen.pick_roots(g, 5, graphgen.root_seed(scale)):
+        check(bfsmi, g, G, int(r))
+
+
+@pytest.mark.parametrize("fmode", [0, 1, 2])
+@pytest.mark.parametrize("ept", [1, 4, 8])
+def test_xcd_slices_forms_and_ept(bfsmi, fmode, ept):
+    g = graphgen.rmat(15)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_XCD_SLICES, 2)
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)
+    for r in graphgen.pick_roots(g, 3, graphgen.root_seed(15)):
+        check(bfsmi, g, G, int(r), mode=fmode, ept=ept)
+
+
+def test_xcd_slices_odd_sizes_and_hubs(bfsmi):
+    # V not a multiple of 1024 or 32, a hub touching every slice, ids on
+    # both sides of the hot-id limit (8192), a disconnected part
+    rng = np.random.default_rng(5)
+    n = 20_011
+    src = np.concatenate([np.zeros(n - 1, np.int64), rng.integers(0, n - 500, 60_000)])
+    dst = np.concatenate([np.arange(1, n), rng.integers(0, n - 500, 60_000)])
+    keep = (src < n - 500) & (dst < n - 500)
+    src, dst = src[keep], dst[keep]
+    tail = np.arange(n - 500, n - 1)
+    g = graphgen.from_edges(n, np.concatenate([src, tail]), np.concatenate([dst, tail + 1]))
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_XCD_SLICES, 2)
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)
+    for r in (0, 1, 9000, n - 500, n - 1):
+        check(bfsmi, g, G, r)
+
+
+def test_xcd_slices_directed(bfsmi):
+    # a directed CSR (rows are out-edges only): sliced levels follow them
+    rng = np.random.default_rng(11)
+    n = 50_000
+    src = rng.integers(0, n, 400_000)
+    dst = (src * 7 + rng.integers(0, 3000, 400_000) ** 2) % n
+    g = graphgen.from_edges(n, src, dst, symmetric=False)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    G.set_option(bfsmi.BFS_OPT_XCD_SLICES, 2)
+    G.set_option(bfsmi.BFS_OPT_LOOP_DRIVER, 1)
+    for r in (0, 17, 4242):
+        check(bfsmi, g, G, r, directed=True)
+
+
+def test_xcd_slices_option_values(bfsmi):
+    g = graphgen.rmat(10)
+    G = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    assert G.get_option(bfsmi.BFS_OPT_XCD_SLICES) == 1
+    for bad in (-1, 3):
+        with pytest.raises(bfsmi.BFSError):
+            G.set_option(bfsmi.BFS_OPT_XCD_SLICES, bad)
