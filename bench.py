@@ -274,6 +274,10 @@ def single_root(args, torch, np, graphgen, bfsmi):
     torch.cuda.synchronize()
     res = search_summary(times, stats, g.V)
     res["ms_per_step"] = total * 1e3 / args.steps
+    # the bitmap levels' claim (0 atomic, 1 flags where they measured faster)
+    # and the XCD-sliced early levels (1 automatic), as the headline ran them
+    res["claim_mode"] = G.get_option(bfsmi.BFS_OPT_CLAIM_MODE) if flags else 0
+    res["xcd_slices"] = G.get_option(bfsmi.BFS_OPT_XCD_SLICES) if flags else 0
     res["levels"] = stats[0].levels
     res["reached"] = stats[0].reached
     res["edges_scanned"] = stats[0].edges_scanned
@@ -768,6 +772,7 @@ def main():
         "config": {"workload": "rmat%d_single_root" % args.scale, "scale": args.scale,
                    "degree_order": not args.no_degree_order,
                    "row_skip": not args.no_degree_order, "parents": True,
+                   "claim_mode": res.get("claim_mode"), "xcd_slices": res.get("xcd_slices"),
                    "edgefactor": 16, "A": 0.57, "B": 0.19, "C": 0.19, "V": g_V, "nnz": g_nnz,
                    "roots": args.roots, "levels_root0": res["levels"],
                    "reached_root0": res["reached"], "edges_scanned_root0": res["edges_scanned"]},
