@@ -593,8 +593,18 @@ __global__ __launch_bounds__(kWG) void k_expand(int32_t V, const int64_t* __rest
             // needed) and a parent from the frontier; when several threads
             // flag it in the same level, each stores a valid parent and one
             // of them remains.  The flag is read first so that most repeat
-            // visits store nothing.
+            // visits store nothing.  Before that, the visited word just read
+            // is stored back with the vertex's bit as a hint: later probes
+            // of the same XCD (its L2 holds the line) then stop at the
+            // visited bit.  The store is a plain one, so two hints to one
+            // word may overwrite each other; that only loses hints (the
+            // flags are the level's result, and the compaction rebuilds the
+            // word from them), never a bit set before the level, which every
+            // stored value carries.
             uint8_t fl[EPT];
+#pragma unroll
+            for (int j = 0; j < EPT; ++j)
+                if (need[j]) vis[vv[j] >> 5] = wd[j] | (1u << (vv[j] & 31));
 #pragma unroll
             for (int j = 0; j < EPT; ++j) fl[j] = need[j] ? found[vv[j]] : (uint8_t)1;
 #pragma unroll
