@@ -197,13 +197,27 @@ __global__ __launch_bounds__(kWG) void k_scan_top(int64_t* __restrict__ bsum, in
     if (dev && ctrl->done) return;
     const int32_t qlen = dev ? ctrl->qlen : qlen_arg;
     const int32_t nblk = (int32_t)(((int64_t)qlen + kScanChunk - 1) / kScanChunk);
+    // kTopItems consecutive block sums per thread and pass: a heavy level
+    // has thousands of blocks, and each pass costs two barriers
+    constexpr int kTopItems = 8;
     int64_t carry = 0;
-    for (int32_t b0 = 0; b0 < nblk; b0 += kWG) {
-        const int32_t b = b0 + threadIdx.x;
-        const int64_t x = b < nblk ? bsum[b] : 0;
+    for (int32_t b0 = 0; b0 < nblk; b0 += kWG * kTopItems) {
+        int64_t x[kTopItems];
+        int64_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kTopItems; ++i) {
+            const int32_t b = b0 + threadIdx.x * kTopItems + i;
+            x[i] = b < nblk ? bsum[b] : 0;
+            sum += x[i];
+        }
         int64_t tot;
-        const int64_t ex = wg_exclusive_scan<int64_t>(x, &tot, s_wave);
-        if (b < nblk) bsum[b] = carry + ex;
+        int64_t run = carry + wg_exclusive_scan<int64_t>(sum, &tot, s_wave);
+#pragma unroll
+        for (int i = 0; i < kTopItems; ++i) {
+            const int32_t b = b0 + threadIdx.x * kTopItems + i;
+            if (b < nblk) bsum[b] = run;
+            run += x[i];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) {
