@@ -244,11 +244,13 @@ hipError_t launch_srv_join(hipStream_t s, int32_t V, int32_t n_join, const int32
                            const int32_t* rank, SeenNext* sn, uint64_t* front,
                            int16_t* const* lane_out, int32_t* lane_start, int32_t* Q, Ctrl* ctrl);
 
-// Persistent multi-source levels for serving batches (msloop.hip).  Zeroed
-// by the host before each launch.
+// Persistent multi-source levels for serving batches (msloop.hip).  Zero
+// before the first launch (the host clears it with the batch state); each
+// launch leaves it zero again.
 struct MsSync {
     uint32_t arrive;     // grid barrier: arrivals (only grows within a launch)
-    uint32_t pad0[31];   // the counters below sit on other lines
+    uint32_t leave;      // workgroups that have finished (the last one re-zeroes the block)
+    uint32_t pad0[30];   // the counters below sit on other lines
     uint32_t fn[3];      // found-list size, by level mod 3
     uint32_t qn[3];      // next-frontier size
     int32_t md[3];       // largest degree in the next frontier
@@ -259,13 +261,14 @@ struct MsSync {
 int ms_small_loop_blocks();
 // Runs up to max_levels serving levels (OUT16 outputs) from ctrl's state;
 // ctrl->steps = levels run; the frontier ends in Qa; found is int32[V]
-// scratch.
+// scratch.  h_ctrl (pinned host memory, or null) receives a copy of the
+// final control block.
 hipError_t launch_ms_small_levels(hipStream_t s, int grid, int32_t V, const int64_t* off,
                                   const int32_t* col, const int32_t* orig, SeenNext* sn,
                                   uint64_t* front, int32_t* Qa, int32_t* Qb, int32_t* found,
                                   int16_t* const* lane_out, const int32_t* lane_start,
-                                  MsSync* sy, Ctrl* ctrl, int32_t max_levels, int32_t qlimit,
-                                  int64_t rlimit, int32_t dlimit);
+                                  MsSync* sy, Ctrl* ctrl, Ctrl* h_ctrl, int32_t max_levels,
+                                  int32_t qlimit, int64_t rlimit, int32_t dlimit);
 
 // Degree-ordered internal relabelling (relabel.hip).  rank[v] is v's
 // internal id (vertices in non-increasing degree order, ties arbitrary),

@@ -238,7 +238,8 @@ __device__ __forceinline__ void ms_phase_totals(MsSync* __restrict__ sy, int cs,
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_ms_small_levels(
+// The levels; every workgroup returns from it exactly once.
+__device__ __forceinline__ void ms_levels_body(
     int32_t V, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const int32_t* __restrict__ orig, SeenNext* __restrict__ sn, uint64_t* __restrict__ front,
     int32_t* __restrict__ Qa, int32_t* __restrict__ Qb, int32_t* __restrict__ found,
@@ -487,6 +488,46 @@ __global__ __launch_bounds__(kWG) void k_ms_small_levels(
     }
 }
 
+// The launch leaves its sync block as it found it (zero) and mirrors the
+// control block into pinned host memory, so a round needs no clearing and
+// no copy of its own: the workgroup that leaves last (after every other
+// has stopped reading the sync block) does both.
+static_assert(sizeof(Ctrl) % sizeof(int4) == 0, "the control block is copied in 16-byte words");
+
+__global__ __launch_bounds__(kWG) void k_ms_small_levels(
+    int32_t V, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ orig, SeenNext* __restrict__ sn, uint64_t* __restrict__ front,
+    int32_t* __restrict__ Qa, int32_t* __restrict__ Qb, int32_t* __restrict__ found,
+    int16_t* const* __restrict__ lane_out, const int32_t* __restrict__ lane_start,
+    MsSync* __restrict__ sy, Ctrl* __restrict__ ctrl, Ctrl* __restrict__ h_ctrl,
+    int32_t max_levels, int32_t qlimit, int64_t rlimit, int32_t dlimit)
+{
+    ms_levels_body(V, off, col, orig, sn, front, Qa, Qb, found, lane_out, lane_start, sy, ctrl,
+                   max_levels, qlimit, rlimit, dlimit);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t k =
+            __hip_atomic_fetch_add(&sy->leave, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == gridDim.x - 1) {
+            sy->arrive = 0;
+            for (int i = 0; i < 3; ++i) {
+                sy->fn[i] = 0;
+                sy->qn[i] = 0;
+                sy->md[i] = 0;
+                sy->rn[i] = 0;
+                sy->alive[i] = 0;
+            }
+            sy->leave = 0;
+            if (h_ctrl) {
+                const int4* src = reinterpret_cast<const int4*>(ctrl);
+                int4* dst = reinterpret_cast<int4*>(h_ctrl);
+                for (int i = 0; i < (int)(sizeof(Ctrl) / sizeof(int4)); ++i) dst[i] = src[i];
+                __threadfence_system();
+            }
+        }
+    }
+}
+
 int ms_small_loop_blocks()
 {
     int n = 0;
@@ -499,13 +540,13 @@ hipError_t launch_ms_small_levels(hipStream_t s, int grid, int32_t V, const int6
                                   const int32_t* col, const int32_t* orig, SeenNext* sn,
                                   uint64_t* front, int32_t* Qa, int32_t* Qb, int32_t* found,
                                   int16_t* const* lane_out, const int32_t* lane_start,
-                                  MsSync* sy, Ctrl* ctrl, int32_t max_levels, int32_t qlimit,
-                                  int64_t rlimit, int32_t dlimit)
+                                  MsSync* sy, Ctrl* ctrl, Ctrl* h_ctrl, int32_t max_levels,
+                                  int32_t qlimit, int64_t rlimit, int32_t dlimit)
 {
     // an ordinary launch of a grid small enough to be resident at once
     hipLaunchKernelGGL(k_ms_small_levels, dim3(grid), dim3(kWG), 0, s, V, off, col, orig, sn, front,
-                       Qa, Qb, found, lane_out, lane_start, sy, ctrl, max_levels, qlimit, rlimit,
-                       dlimit);
+                       Qa, Qb, found, lane_out, lane_start, sy, ctrl, h_ctrl, max_levels, qlimit,
+                       rlimit, dlimit);
     return hipGetLastError();
 }
 

@@ -527,6 +527,8 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
     if (P.reset)
         bad |= launch_srv_reset(G.stream, g->num_cus * 4, g->V, B->sn, B->front, B->touched,
                                 B->ctrl) != hipSuccess;
+    if (P.fresh || P.reset)  // each persistent launch then leaves it zero
+        bad |= hipMemsetAsync(B->msync, 0, sizeof(MsSync), G.stream) != hipSuccess;
     else if (P.clear)
         bad |= launch_srv_clear(G.stream, g->num_cus * 4, g->V, B->sn, P.clear) != hipSuccess;
     for (int i = 0; i < P.n_join; ++i)
@@ -562,16 +564,17 @@ void bfs_server::execute(SrvGraph& G, const StepPlan& P)
         B->round_levels = kRoundLevels[P.round];
         if (P.persist) {
             ++persist_inflight;
-            bad |= hipMemsetAsync(B->msync, 0, sizeof(MsSync), G.stream) != hipSuccess;
+            // the kernel copies the control block into G.h_ctrl itself
             bad |= launch_ms_small_levels(G.stream, ms_grid, g->V, g->s_off, g->s_col, g->orig,
                                           B->sn, B->front, B->q[0], B->q[1], B->deg, B->lane_out,
-                                          B->lane_start, B->msync, B->ctrl, B->round_levels,
-                                          kMsQLimit, kMsRLimit, kMsDLimit) != hipSuccess;
+                                          B->lane_start, B->msync, B->ctrl, G.h_ctrl,
+                                          B->round_levels, kMsQLimit, kMsRLimit,
+                                          kMsDLimit) != hipSuccess;
         } else {
             bad |= !B->round[P.round] || hipGraphLaunch(B->round[P.round], G.stream) != hipSuccess;
+            bad |= hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                                  G.stream) != hipSuccess;
         }
-        bad |= hipMemcpyAsync(G.h_ctrl, B->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, G.stream) !=
-               hipSuccess;
         bad |= hipEventRecord(G.ev, G.stream) != hipSuccess;
         B->in_flight = true;
     }
@@ -631,7 +634,8 @@ void bfs_server::run()
         bool waiting = false;
         for (const auto& G : graphs) waiting |= G.batch != nullptr || !G.pending.empty();
         if (waiting && !stalled) {
-            // poll in-flight rounds at a fine grain
+            // poll in-flight rounds at a fine grain (a busy poll was measured:
+            // it slowed the other graphs' rounds more than it sped up these)
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(20));
         } else {
