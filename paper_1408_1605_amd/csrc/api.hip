@@ -531,6 +531,9 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
     int64_t reached = 1, edges = 0, xbytes = 0, xalg = 0;
     int32_t nlevels = 1, bitmap_levels = 0, xlaunches = 0, dev_levels = 0;
     const bool dev_ok = g->loop_driver != 1 && g->small_grid > 0;
+    // the persistent loop's sync block: zero once per search (each launch
+    // leaves it zero; the workspace's contents before the search are unknown)
+    if (dev_ok) BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
     bool dev_left = false;  // the persistent loop just handed a heavy level back
     // direction-optimizing mode: the degree sum of the frontier a bottom-up
     // step searches from, and the size of the frontier before it
@@ -578,8 +581,6 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
             continue;
         }
         if (dev_ok && !dev_left && qlen <= g->small_limit) {
-            BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
-            BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
             BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
                                             g->vis, g->vis_old, g->q[cur], g->q[cur ^ 1], lv_s,
                                             pa_s, g->small_sync, g->small_side, g->ctrl, qlen,
@@ -698,8 +699,6 @@ int run_host_loop(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents,
         // levels after a heavy one costs no extra host round trip
         const bool spec = dev_ok && !dir_opt;
         if (spec) {
-            BFS_HIP_TRY(hipMemsetAsync(g->small_sync, 0, sizeof(SmallSync), s));
-            BFS_HIP_TRY(hipMemsetAsync(&g->ctrl->r_total, 0, sizeof(int64_t), s));
             BFS_HIP_TRY(launch_small_levels(s, g->small_grid, g->V, g->s_off, g->s_col, g->orig,
                                             g->vis, g->vis_old, Qn, g->q[cur], lv_s, pa_s,
                                             g->small_sync, g->small_side, g->ctrl, -1, lvl + 1,

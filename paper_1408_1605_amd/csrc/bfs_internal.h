@@ -121,15 +121,18 @@ hipError_t launch_slice_scan(hipStream_t s, int grid, const int32_t* Q, int32_t 
 // The grid barrier's counter and the per-level counters sit on separate
 // 128-byte lines, so the barrier's polling does not queue behind the
 // counters' atomics.
+// Zero before a search's first launch; each launch leaves it zero again.
 struct SmallSync {
     uint32_t arrive;   // grid barrier: arrivals (only grows within a launch)
-    uint32_t pad0[31];
+    uint32_t leave;    // workgroups that have finished (the last one re-zeroes the block)
+    uint32_t pad0[30];
     uint32_t qn[3];    // next-frontier size, by level mod 3
     uint32_t pad1[29];
     int32_t md[3];     // largest degree in the next frontier
     int32_t pad2[29];
     int64_t rn[3];     // edges of the next frontier
-    int64_t pad3[13];
+    int64_t edges;     // edges the launch expanded (to ctrl->r_total at the end)
+    int64_t pad3[12];
 };
 // Row start, degree and caller id of each frontier entry, one set per
 // queue (cap entries each), written by the workgroup that claims the vertex

@@ -64,7 +64,8 @@ __device__ __forceinline__ bool grid_sync(SmallSync* sy, uint32_t nwg, uint32_t*
     return s_ok != 0;
 }
 
-__global__ __launch_bounds__(kWG) void k_small_levels(
+// The levels; every workgroup returns from it exactly once.
+__device__ __forceinline__ void small_levels_body(
     int32_t V, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const int32_t* __restrict__ orig, uint32_t* __restrict__ vis, uint32_t* __restrict__ vis_old,
     int32_t* __restrict__ Qa, int32_t* __restrict__ Qb, int32_t* __restrict__ level,
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
         }
     }
     if (t == 0 && my_edges)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&ctrl->r_total), (unsigned long long)my_edges);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&sy->edges), (unsigned long long)my_edges);
     if (w == 0 && t == 0 && code != 3) {
         ctrl->done = code;
         ctrl->qlen = qlen;
@@ -362,6 +363,36 @@ __global__ __launch_bounds__(kWG) void k_small_levels(
         ctrl->steps = step;
         ctrl->reached = reached;
         ctrl->levels = code == 1 ? step - 1 : step;
+    }
+}
+
+// The launch leaves its sync block as it found it (zero), so it needs no
+// clearing of its own: the workgroup that leaves last (after every other has
+// stopped reading the block) publishes the edge total and clears the block.
+__global__ __launch_bounds__(kWG) void k_small_levels(
+    int32_t V, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ orig, uint32_t* __restrict__ vis, uint32_t* __restrict__ vis_old,
+    int32_t* __restrict__ Qa, int32_t* __restrict__ Qb, int32_t* __restrict__ level,
+    int32_t* __restrict__ parent, SmallSync* __restrict__ sy, SmallSide side,
+    Ctrl* __restrict__ ctrl, int32_t qlen0, int32_t lvl0, int32_t qlimit, int64_t rlimit, int32_t dlimit)
+{
+    small_levels_body(V, off, col, orig, vis, vis_old, Qa, Qb, level, parent, sy, side, ctrl, qlen0,
+                      lvl0, qlimit, rlimit, dlimit);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t k =
+            __hip_atomic_fetch_add(&sy->leave, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == gridDim.x - 1) {
+            ctrl->r_total = sy->edges;
+            sy->arrive = 0;
+            for (int i = 0; i < 3; ++i) {
+                sy->qn[i] = 0;
+                sy->md[i] = 0;
+                sy->rn[i] = 0;
+            }
+            sy->edges = 0;
+            sy->leave = 0;
+        }
     }
 }
 
