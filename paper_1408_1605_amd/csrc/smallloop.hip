@@ -10,11 +10,13 @@
 //     slice's degrees, row starts and caller ids in LDS with a prefix sum,
 //     and maps the slice's edges to threads by binary search in it
 //     (Section 3.4, within the slice, so no grid-wide scan is needed);
-//   - claims go straight to the atomicOr of Algorithm 3 (the plain-read
-//     probe that the heavy levels use would add one dependent memory round
-//     trip per level, and these levels are bound by round trips, not by
-//     atomic throughput); winners write level and parent, and append to the
-//     next queue with one reservation per workgroup and tile;
+//   - on levels of at most 64K edges claims go straight to the atomicOr of
+//     Algorithm 3 (the plain-read probe would add one dependent memory round
+//     trip per level, and such levels are bound by round trips, not by
+//     atomic throughput); levels with more edges probe first, since hub rows
+//     would queue their claims on a few bitmap lines; winners write level
+//     and parent, and append to the next queue with one reservation per
+//     workgroup and tile;
 //   - a winner also stores its row start, degree and caller id beside its
 //     queue slot, so the next level stages its frontier without looking
 //     them up in the CSR;
@@ -32,6 +34,7 @@ constexpr int kSmallEPT = 4;
 constexpr int kSmallTile = kWG * kSmallEPT;
 constexpr int kSmallStage = 1024;  // frontier entries staged per pass (4 per thread)
 constexpr uint32_t kSpinCap = 1u << 24;
+constexpr int64_t kSmallProbeEdges = 1 << 16;  // levels with more edges probe before claiming
 static_assert(kWG == 256, "per-wave partials below assume four waves");
 
 // Grid-wide barrier on a counter that only grows (reset to zero before the
@@ -131,9 +134,11 @@ __device__ __forceinline__ void small_levels_body(
         if (t == 0) ctrl->err = 4;
         return;
     }
+    int64_t cur_rn;  // edges of the frontier being expanded
     {
         // slot 2 is next reset during level 1, after every workgroup read it
         const int64_t rn = __hip_atomic_load(&sy->rn[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cur_rn = rn;
         const int32_t md = __hip_atomic_load(&sy->md[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (rn > rlimit || md > dlimit) {
             if (w == 0 && t == 0) {
@@ -163,6 +168,10 @@ __device__ __forceinline__ void small_levels_body(
         int32_t* __restrict__ out_deg = side.deg[par ^ 1];
         int32_t* __restrict__ out_id = side.id[par ^ 1];
         const int cs = step % 3;  // counters of this level
+        // a level with many edges reads the target's bitmap word first and
+        // claims only unset bits: on hub rows the claims of a bare atomicOr
+        // would queue on a few bitmap lines
+        const bool probe = cur_rn > kSmallProbeEdges;
         if (w == 0 && t == 0) {
             // the next level's counters were last read two barriers ago
             const int nx = (step + 1) % 3;
@@ -248,10 +257,19 @@ __device__ __forceinline__ void small_levels_body(
                     vv[j] = col[s_base[i] + e0 + sc];
                 }
                 uint32_t old[kSmallEPT];
+                if (probe) {
 #pragma unroll
-                for (int j = 0; j < kSmallEPT; ++j) {
-                    old[j] = ~0u;
-                    if (ok[j]) old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
+                    for (int j = 0; j < kSmallEPT; ++j) old[j] = ok[j] ? vis[vv[j] >> 5] : ~0u;
+#pragma unroll
+                    for (int j = 0; j < kSmallEPT; ++j)
+                        if (!(old[j] & (1u << (vv[j] & 31))))
+                            old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kSmallEPT; ++j) {
+                        old[j] = ~0u;
+                        if (ok[j]) old[j] = atomicOr(vis + (vv[j] >> 5), 1u << (vv[j] & 31));
+                    }
                 }
                 bool win[kSmallEPT];
                 uint64_t mask[kSmallEPT];
@@ -340,6 +358,7 @@ __device__ __forceinline__ void small_levels_body(
         const uint32_t qn = __hip_atomic_load(&sy->qn[cs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int64_t rn = __hip_atomic_load(&sy->rn[cs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int32_t md = __hip_atomic_load(&sy->md[cs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cur_rn = rn;
         ++step;
         ++lvl;
         reached += qn;
