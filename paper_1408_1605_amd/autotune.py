@@ -12,8 +12,11 @@ Every candidate is run on the tuning roots first and its levels are compared
 element by element with expected levels that the caller supplies (the CPU
 oracle's, computed outside this package); a candidate that differs is
 recorded as failing parity and never timed.  Of the passing candidates the
-fastest (mean wall time per search over `reps` rounds) is chosen.  Results
-are cached as JSON per (GPU architecture, graph class, scale).
+fastest (mean wall time per search over `reps` rounds) is chosen, unless the
+configuration the handle had before tuning (the library defaults, unless
+the caller changed them) is within TIE of it: near-equal candidates would
+otherwise trade places from run to run on timing noise alone.  Results are
+cached as JSON per (GPU architecture, graph class, scale).
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ SINGLE_SPACE = {"ept": (1, 2, 4, 8), "summary": (1, 2), "grid_wgs": (4, 8),
                 "loop_limit": (4096, 16384, 65536)}
 DIRECTION_SPACE = {"alpha": (4, 8, 14, 24, 48), "beta": (8, 24, 72)}
 BATCH_SPACE = {"batch_tile": (256, 512, 1024, 2048)}
+TIE = 0.02  # relative time within which the starting configuration is kept
 
 _OPT = {"ept": B.BFS_OPT_EDGES_PER_THREAD, "summary": B.BFS_OPT_VISITED_SUMMARY,
         "grid_wgs": B.BFS_OPT_GRID_WGS, "loop_limit": B.BFS_OPT_LOOP_LIMIT,
@@ -88,9 +92,20 @@ def _tune(G, cands, run_one, outputs, expected_dev, reps, log, tag):
             log("tune %s %s" % (tag, row))
     for k, v in saved.items():
         B.bfs_set_option(G.handle, _OPT[k], v)
+    return _pick(table, saved), table
+
+
+def _pick(table, start, tie: float = TIE):
+    """The fastest row of table that passed parity; the row whose knobs equal
+    start instead when its time is within tie of the fastest."""
     good = [t for t in table if t["parity"]]
-    best = min(good, key=lambda t: t["ms"]) if good else None
-    return best, table
+    if not good:
+        return None
+    best = min(good, key=lambda t: t["ms"])
+    for t in good:
+        if all(t.get(k) == v for k, v in start.items()) and t["ms"] <= best["ms"] * (1.0 + tie):
+            return t
+    return best
 
 
 def tune_single(G, roots, expected, reps: int = 2, log=None, space: dict | None = None,
