@@ -328,6 +328,52 @@ def test_serve_wide_deep_rounds(bfsmi):
     h.close()
 
 
+def _triangulated_grid(side):
+    # a side x side lattice with one diagonal per cell: deep (about 2 * side
+    # levels from a corner) and full of triangles, so vertices at one depth
+    # are adjacent and a search finds some of them twice in one level
+    i = np.arange(side * side, dtype=np.int64).reshape(side, side)
+    src = np.concatenate([i[:, :-1].ravel(), i[:-1, :].ravel(), i[:-1, :-1].ravel()])
+    dst = np.concatenate([i[:, 1:].ravel(), i[1:, :].ravel(), i[1:, 1:].ravel()])
+    return graphgen.from_edges(side * side, src, dst)
+
+
+def test_serve_deep_graph_with_same_level_edges(bfsmi):
+    # the persistent rounds finalize one level and expand the next in the
+    # same phase, reading other vertices' seen masks while they change; on a
+    # graph with edges inside a level that admits spurious candidates, which
+    # their own finalize must drop: every result must be the oracle's
+    g = _triangulated_grid(300)
+    h = bfsmi.Graph.from_csr(g.off, g.col, flags=bfsmi.BFS_DEGREE_ORDER)
+    arena = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = bfsmi.bfs_server_create(arena, max_lanes=64, max_inflight=4, flags=0)
+    gid = bfsmi.bfs_server_add_graph(s, h.handle)
+    rng = np.random.default_rng(33)
+    # the first two queries teach the server that the graph is deep
+    first = [bfsmi.bfs_submit(s, gid, int(r)) for r in rng.integers(0, g.V, size=2)]
+    drain_completed(bfsmi, s, first, timeout=120.0)
+    roots = [int(r) for r in rng.integers(0, g.V, size=40)]
+    ts = []
+    for k, r in enumerate(roots):
+        ts.append(bfsmi.bfs_submit(s, gid, r))
+        if k % 8 == 7:
+            time.sleep(0.003)  # later queries join batches already running
+    _say("same-level edges: %d queries submitted" % len(ts))
+    drain_completed(bfsmi, s, ts, timeout=120.0)
+    for t, r in zip(ts, roots):
+        got = np.empty(g.V, dtype=np.int32)
+        code, tm = bfsmi.bfs_poll(s, t, got)
+        assert code == bfsmi.BFS_OK
+        assert np.array_equal(got, oracle.bfs(g.off, g.col, r).level), r
+    st = bfsmi.bfs_server_get_stats(s)
+    _say("same-level edges: rounds %d persistent %d" % (st.rounds, st.persistent_rounds))
+    assert st.failed == 0
+    assert st.persistent_rounds > 0
+    bfsmi.bfs_server_destroy(s)
+    h.close()
+
+
 def test_serve_drain_reports_uncollected_results(bfsmi, pool):
     # room for one batch state and three results: after three queries finish
     # without being polled, nothing else can be admitted, so drain must
