@@ -55,6 +55,7 @@ import math
 import os
 import platform
 import sys
+import threading
 import time
 
 # The serving section drives one stream per resident graph; HIP maps a
@@ -571,6 +572,34 @@ def serve_section(args, torch, np, graphgen, bfsmi):
     warm_ns = t_start + int(warm * 1e9)
     end_ns = t_start + int((warm + dur) * 1e9)
     st0 = None
+    # Each query's latency runs from its scheduled arrival.  By default this
+    # thread submits the due arrivals between collecting results (a device
+    # delivery is synchronous, so a slow one delays the next submissions and
+    # that delay counts as latency); --serve-submit-thread gives submission a
+    # thread of its own that keeps to the schedule.
+    lock = threading.Lock()
+    submitter = None
+    if args.serve_submit_thread:
+        def submit_loop():
+            at = t_start
+            for k in range(n):
+                if at >= end_ns:
+                    break
+                while True:
+                    left = at - time.monotonic_ns()
+                    if left <= 0:
+                        break
+                    time.sleep(min(left / 1e9, 0.0002))
+                gk = int(gsel[k])
+                ck = nonzero[gk]
+                rk = int(ck[int(rsel[k] * len(ck))])
+                with lock:
+                    tk = bfsmi.bfs_submit(s, ids[gk], rk)
+                    pending[tk] = (at, gk, rk)
+                at += int(gaps[k] * 1e9)
+        submitter = threading.Thread(target=submit_loop, daemon=True)
+        submitter.start()
+        i = n  # the loop below only collects
     while True:
         now = time.monotonic_ns()
         if st0 is None and now >= warm_ns:
@@ -584,7 +613,8 @@ def serve_section(args, torch, np, graphgen, bfsmi):
             sched += int(gaps[i] * 1e9)
             i += 1
         for t in bfsmi.bfs_server_completed(s):
-            arrive, gi, root = pending.pop(t)
+            with lock:
+                arrive, gi, root = pending.pop(t)
             code, tm = bfsmi.bfs_poll(s, t, dst[gi])
             if arrive >= warm_ns and len(rec) % 97 == 0 and len(samples) < 64:
                 # kept for the check against the oracle after the window (a
@@ -595,11 +625,18 @@ def serve_section(args, torch, np, graphgen, bfsmi):
                             (tm.done_ns - tm.admit_ns) / 1e6, tm.lanes_in_batch, tm.levels))
                 if tm.done_ns <= end_ns:
                     done_in_window += 1
-        if sched >= end_ns and not pending:
+        if submitter is not None:
+            if not submitter.is_alive():
+                with lock:
+                    if not pending:
+                        break
+        elif sched >= end_ns and not pending:
             break
         if time.monotonic_ns() > end_ns + int(30e9):
             break
         time.sleep(0.0001)
+    if submitter is not None:
+        submitter.join(timeout=5.0)
     st1 = bfsmi.bfs_server_get_stats(s)
     bfsmi.bfs_server_destroy(s)
     for h in handles:
@@ -626,6 +663,8 @@ def serve_section(args, torch, np, graphgen, bfsmi):
            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
            "max_ms": round(max(lat), 3) if lat else None, "unfinished": len(pending),
            "delivery": "int32 levels into a client device buffer",
+           "submission": ("own thread, on schedule" if args.serve_submit_thread
+                          else "between deliveries, late arrivals count as latency"),
            "parity": {"sampled_tickets": s_n, "tickets_ok": int(s_ok),
                       "kinds": sorted({kinds[gi] for gi in by_graph})}}
     for kind in ("rmat", "grid"):
@@ -687,6 +726,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving section")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-submit-thread", action="store_true",
+                    help="submit serving queries from a thread of their own, on schedule")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-arena-gb", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
