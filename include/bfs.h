@@ -411,7 +411,10 @@ int bfs_submit(bfs_server *s, int32_t graph_id, int32_t root, uint64_t *ticket);
  * be host memory or device memory of the server's device.  A device buffer
  * is filled by a widening kernel on the device's default (null) stream, so
  * it is ordered after work the caller queued there, and never crosses
- * PCIe.  The call returns after the levels are written.  BFS_ERR_TICKET for unknown or retired
+ * PCIe.  The call returns after the levels are written (under load that
+ * kernel can wait about a millisecond behind other graphs' work in the
+ * shared hardware queues, so a client that must keep submitting on time
+ * should poll from another thread).  BFS_ERR_TICKET for unknown or retired
  * tickets.
  */
 int bfs_poll(bfs_server *s, uint64_t ticket, int32_t *dst_levels, bfs_timing *t);
