@@ -735,8 +735,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the single-GPU search has no "
-              "multi-GPU path); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the search runs on one GPU only (it has no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
